@@ -1,0 +1,59 @@
+"""Input generator against its published definition, and the oracle against
+the stored fixtures written by tests/golden/make_golden.py."""
+import json
+import os
+
+import numpy as np
+
+import oracle
+import wfgen
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_splitmix64_reference_vector():
+    lines = [l.strip() for l in open(os.path.join(GOLD, "splitmix64_vectors.txt")) if l.strip() and not l.startswith("#")]
+    seed = int(lines[0].split()[1])
+    want = np.array([int(x) for x in lines[1:]], dtype=np.uint64)
+    assert np.array_equal(wfgen.splitmix64(seed, np.arange(len(want))), want)
+
+
+def test_cells_value_ranges_and_banding():
+    c = wfgen.cells(9, 300, 257, "f32")
+    assert c.dtype == np.float32 and (c >= 0).all() and (c < 1).all()
+    # exact multiples of 2^-24
+    assert np.array_equal(np.floor(c.astype(np.float64) * 2 ** 24), c.astype(np.float64) * 2 ** 24)
+    ci = wfgen.cells(9, 300, 257, "i32")
+    assert ci.min() >= 0 and ci.max() <= 255
+    assert np.array_equal(wfgen.cells(9, 300, 257, "f32", 100, 50), c[100:150])
+    # roughly uniform
+    assert abs(float(c.mean()) - 0.5) < 0.01
+
+
+def test_batch_and_serving_recipes():
+    shapes = wfgen.batch_shapes(4096)
+    ms = np.array([s[0] for s in shapes]); ns = np.array([s[1] for s in shapes])
+    assert ms.min() >= 64 and ms.max() <= 2048 and ns.min() >= 64 and ns.max() <= 2048
+    # log-uniform: median near sqrt(64*2049)
+    assert 250 < np.median(ms) < 470
+    assert shapes == wfgen.batch_shapes(4096)
+    reqs = wfgen.serving_requests(1000, 200.0)
+    ts = np.array([r[0] for r in reqs])
+    assert (np.diff(ts) >= 0).all() and abs(ts[-1] / 999 - 1 / 200.0) < 0.2 / 200.0 * 5
+
+
+def test_oracle_reproduces_golden():
+    g = json.load(open(os.path.join(GOLD, "sweep_small.json")))
+    for case in g["cases"]:
+        seed, m, n = case["seed"], case["m"], case["n"]
+        c = wfgen.cells(seed, m, n, "f32")
+        ci = wfgen.cells(seed, m, n, "i32")
+        for rule in ("min", "max"):
+            exp = case[rule]
+            lr, lc = oracle.sweep(c, rule, "f64", full=False)
+            assert lr.tolist() == exp["f64_last_row"] and lc.tolist() == exp["f64_last_col"]
+            lr32, lc32 = oracle.sweep(c, rule, "f32", full=False)
+            assert lr32.view(np.uint32).tolist() == exp["f32_last_row_bits"]
+            assert lc32.view(np.uint32).tolist() == exp["f32_last_col_bits"]
+            lri, lci = oracle.sweep(ci, rule, "i64", full=False)
+            assert lri.tolist() == exp["i64_last_row"] and lci.tolist() == exp["i64_last_col"]

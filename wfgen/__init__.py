@@ -1,0 +1,94 @@
+"""Seeded synthetic inputs for the wavefront sweep (shared by the oracle side
+and the GPU side; holds none of the sweep's arithmetic).
+
+Every per-cell input is a pure function of (seed, linear index k = i*n + j),
+so a grid can be generated in any order, in bands, or on the device, and the
+CPU and GPU copies are bit-identical.
+
+Generator: SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom
+number generators", OOPSLA 2014).  The k-th output of a SplitMix64 stream
+seeded with `seed` is  mix64(seed + (k+1) * GAMMA)  with
+    mix64(z): z ^= z >> 30; z *= 0xBF58476D1CE4E5B9;
+              z ^= z >> 27; z *= 0x94D049BB133111EB; z ^= z >> 31
+(all arithmetic mod 2^64).
+
+Mapping to cell values:
+  float32: top 24 bits, (x >> 40) * 2^-24   -> uniform on [0, 1), exact in fp32
+  int32:   low 8 bits,  x & 255             -> uniform on {0, ..., 255}
+
+Workload recipes (sizes, seeds, arrival times) for the benchmark
+configurations also live here, because they are input generation too.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, k: np.ndarray) -> np.ndarray:
+    """k-th outputs (uint64 array) of the SplitMix64 stream seeded with `seed`."""
+    k = np.asarray(k, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + (k + np.uint64(1)) * GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def _to_dtype(x: np.ndarray, dtype: str) -> np.ndarray:
+    if dtype == "f32":
+        return ((x >> np.uint64(40)).astype(np.float64) * (2.0 ** -24)).astype(np.float32)
+    if dtype == "i32":
+        return (x & np.uint64(255)).astype(np.int32)
+    raise ValueError(f"unknown dtype {dtype!r}")
+
+
+def cells(seed: int, m: int, n: int, dtype: str = "f32", row0: int = 0, rows: int | None = None) -> np.ndarray:
+    """Rows [row0, row0+rows) of the m x n input grid for `seed` (row-major, C-contiguous)."""
+    if rows is None:
+        rows = m - row0
+    if not (0 <= row0 and rows >= 0 and row0 + rows <= m):
+        raise ValueError("row band out of range")
+    i = np.arange(row0, row0 + rows, dtype=np.uint64)[:, None]
+    j = np.arange(n, dtype=np.uint64)[None, :]
+    k = i * np.uint64(n) + j
+    return _to_dtype(splitmix64(seed, k), dtype)
+
+
+def vector(seed: int, length: int, dtype: str = "f32") -> np.ndarray:
+    """A seeded 1-D vector (used for explicit top/left boundaries in tests)."""
+    return _to_dtype(splitmix64(seed, np.arange(length, dtype=np.uint64)), dtype)
+
+
+def batch_shapes(count: int = 4096, lo: int = 64, hi: int = 2048, seed: int = 4):
+    """(m, n) pairs, each drawn independently log-uniform on [lo, hi]:
+    floor(exp(U[ln lo, ln(hi+1)))).  Uses numpy's PCG64 so the recipe is
+    reproducible from (count, lo, hi, seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = rng.uniform(math.log(lo), math.log(hi + 1), size=(count, 2))
+    mn = np.floor(np.exp(u)).astype(np.int64)
+    mn = np.clip(mn, lo, hi)
+    return [(int(a), int(b)) for a, b in mn]
+
+
+def batch_seed(g: int) -> int:
+    """Seed of grid g in a batch."""
+    return 1000 + g
+
+
+def serving_requests(count: int, rate_per_s: float, lo: int = 128, hi: int = 8192, seed: int = 5):
+    """Poisson arrivals of square grids: returns [(t_arrival_s, n, seed_of_grid)].
+    Inter-arrival times are exponential with mean 1/rate; n is log-uniform on
+    [lo, hi]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gaps = rng.exponential(1.0 / rate_per_s, size=count)
+    t = np.cumsum(gaps) - gaps[0]
+    u = rng.uniform(math.log(lo), math.log(hi + 1), size=count)
+    ns = np.clip(np.floor(np.exp(u)).astype(np.int64), lo, hi)
+    return [(float(a), int(b), 50000 + q) for q, (a, b) in enumerate(zip(t, ns))]
