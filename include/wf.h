@@ -1,0 +1,197 @@
+/*
+ * wf.h -- C ABI of libwf, the anti-diagonal wavefront sweep for AMD MI355X
+ * (gfx950).
+ *
+ * THE OPERATION
+ *   An m x n grid H is computed from a per-cell input c.  Each cell depends on
+ *   its north (i-1, j), west (i, j-1) and north-west (i-1, j-1) neighbours:
+ *
+ *       H[i][j] = c[i][j] + op(N, W, NW),      op = min  (WF_RULE_MIN)
+ *                                               op = max  (WF_RULE_MAX)
+ *
+ *   with boundary row/column
+ *       N  = i == 0 ? top[j+1] : H[i-1][j]
+ *       W  = j == 0 ? left[i]  : H[i][j-1]
+ *       NW = i == 0 ? top[j]   : (j == 0 ? left[i-1] : H[i-1][j-1]).
+ *   top has n+1 values (top[0] is the corner H[-1][-1]), left has m values.
+ *   A NULL top/left selects the default boundary: the corner is 0 and every
+ *   other boundary value is "absent" (+inf for min, -inf for max; for int32
+ *   INT32_MAX and INT32_MIN+1), so H[i][j] is the min (max) over all monotone
+ *   lattice paths (steps S, E, SE) from (0,0) to (i,j) of the sum of c.
+ *   The grid resolves in m+n-1 anti-diagonal wavefronts.
+ *
+ *   Source: arxiv 2501.05938 states no sweep of its own; the cell rule above
+ *   is this library's reading of the task it serves.  The max rule is the
+ *   one the paper's equations fix: with the three copy/compute engines as
+ *   columns and stream chunks as rows it is the flow-shop recurrence whose
+ *   identical-rows closed form is the streamed-time model of Eq. 2
+ *   (Section 2.2).  Problem parameters follow that paper's statement of its
+ *   own problem: a size (here m, n), a precision (FP32 here; its FP64 is not
+ *   offered), the caller's stream, and tuning knobs in place of its threads
+ *   per block and sub-system size.
+ *
+ * ARITHMETIC
+ *   WF_F32: float32 inputs and outputs, exactly one IEEE round-to-nearest-even
+ *   addition per cell after an exact min/max, so results are bit-identical to
+ *   a sequential fp32 loop in any evaluation order.  Inputs must be free of
+ *   NaN; a NaN input gives unspecified values and may end in WF_ETIMEDOUT.
+ *   WF_I32: int32 inputs and outputs, wrapping 32-bit addition; results are
+ *   exact while every partial path sum stays inside (INT32_MIN, INT32_MAX).
+ *   The value INT32_MIN is reserved (never a valid result).
+ *
+ * MEMORY AND OWNERSHIP
+ *   All data pointers in wf_problem are DEVICE pointers on the context's
+ *   device, owned by the caller; the library reads/writes them only inside
+ *   the work it enqueues and keeps no reference after that work completes.
+ *   Layouts are row-major with leading dimensions in ELEMENTS (ld >= n).
+ *   The context owns its workspace (handoff rows, counters, descriptor
+ *   tables); the server owns the output slots it hands out.
+ *
+ * ASYNCHRONY
+ *   wf_solve / wf_solve_batched enqueue on `stream` (a hipStream_t, or NULL
+ *   for the legacy default stream) and return; results are valid once the
+ *   stream's work up to that point has completed.  Errors raised by the
+ *   device (watchdog) are reported by the next call on the same context.
+ *
+ * ERRORS
+ *   Every call returns a wf_status; nothing throws or aborts across the ABI.
+ *   wf_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef WF_H
+#define WF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int wf_status;
+enum {
+  WF_OK = 0,
+  WF_PENDING = 1,        /* wf_poll: request not finished yet */
+  WF_EINVAL = -1,        /* bad argument (sizes, NULL required pointer, ld < n, unknown enum) */
+  WF_ENOMEM = -2,        /* device or host allocation failed */
+  WF_E2BIG = -3,         /* request larger than the server's HBM budget */
+  WF_EHIP = -4,          /* HIP runtime error; message kept in wf_last_error() */
+  WF_ETIMEDOUT = -5,     /* device watchdog fired (a wait exceeded the limit) */
+  WF_ENOTFOUND = -6,     /* unknown server ticket */
+  WF_ESHUTDOWN = -7,     /* server is shutting down / was destroyed */
+  WF_EUNSUPPORTED = -8   /* valid but unsupported combination */
+};
+
+enum { WF_F32 = 0, WF_I32 = 1 };              /* element type of cost, top, left and outputs */
+enum { WF_RULE_MIN = 0, WF_RULE_MAX = 1 };    /* op of the cell rule */
+enum { WF_MODE_FULL = 0, WF_MODE_EDGES = 1 }; /* FULL writes all of H; EDGES writes only last row/col/cell */
+
+typedef struct wf_problem {
+  int64_t m, n;            /* grid rows and columns, >= 1 (0 means nothing to do) */
+  int32_t dtype;           /* WF_F32 or WF_I32 */
+  int32_t rule;            /* WF_RULE_MIN or WF_RULE_MAX */
+  int32_t mode;            /* WF_MODE_FULL or WF_MODE_EDGES */
+  int32_t flags;           /* must be 0 */
+  const void* cost;        /* device, m x n, row stride ld_cost elements; required */
+  int64_t ld_cost;
+  void* out;               /* device, m x n, row stride ld_out; required in FULL mode, ignored in EDGES */
+  int64_t ld_out;
+  const void* top;         /* device, n+1 values, or NULL for the default boundary */
+  const void* left;        /* device, m values, or NULL for the default boundary */
+  void* last_row;          /* device, n values, or NULL (required in EDGES mode unless last_col or final_cell given) */
+  void* last_col;          /* device, m values, or NULL */
+  void* final_cell;        /* device, 1 value, or NULL */
+} wf_problem;
+
+typedef struct wf_tuning {
+  int32_t waves_per_wg;    /* compute waves per workgroup: 1, 2 or 4 (0 = automatic) */
+  int32_t max_wgs;         /* persistent workgroups per launch (0 = automatic) */
+  int32_t order;           /* batched work order: 0 = automatic, 1 = grid-major, 2 = interleaved by band */
+  int32_t use_graph;       /* batched: 1 = capture and replay a hipGraph (default), 0 = plain launch, -1 = automatic */
+  int32_t reserved[4];     /* must be 0 */
+} wf_tuning;
+
+typedef struct wf_ctx wf_ctx;
+
+/* Create a context on HIP device `device`.  One context per host thread, or
+ * guard it with your own lock. */
+wf_status wf_init(int device, wf_ctx** out);
+/* Wait for the context's outstanding work and free its workspace. */
+wf_status wf_destroy(wf_ctx* ctx);
+
+/* Sweep one grid with one persistent kernel launch on `stream`. */
+wf_status wf_solve(wf_ctx* ctx, const wf_problem* p, void* stream);
+
+/* Sweep `count` independent grids of any sizes in one persistent launch on
+ * `stream`; the bands of all grids are packed into one work list so the thin
+ * first and last diagonals of one grid overlap the wide middle of another.
+ * `t` may be NULL (tuned defaults from the context's tuning table).  The
+ * launch is captured in a hipGraph and replayed when the same batch shape
+ * (count, sizes, dtype/rule/mode) is solved again. */
+wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t count, const wf_tuning* t, void* stream);
+
+/* Wait for all work this context has enqueued and return WF_ETIMEDOUT if the
+ * device watchdog fired in any of it, WF_OK otherwise.  (wf_solve and
+ * wf_solve_batched report such an error too, on the first call after the
+ * failed launch has finished.) */
+wf_status wf_check(wf_ctx* ctx);
+
+/* ---------------------------------------------------------------- serving */
+typedef struct wf_server wf_server;
+
+typedef struct wf_server_opts {
+  int64_t hbm_budget_bytes;  /* bytes of device memory the server may hold for requests (0 = 64 GiB) */
+  int32_t max_inflight;      /* launches allowed in flight at once (0 = 4), each on its own stream */
+  int32_t max_batch;         /* requests per launch at most (0 = 256) */
+  int32_t reserved[4];       /* must be 0 */
+} wf_server_opts;
+
+enum { WF_INPUT_DEVICE = 0, WF_INPUT_HOST = 1 };
+
+typedef struct wf_request {
+  int64_t m, n;
+  int32_t dtype, rule, mode;
+  int32_t input_kind;        /* WF_INPUT_DEVICE: `input` is a device pointer the caller keeps valid
+                                until wf_poll reports completion; WF_INPUT_HOST: host memory copied
+                                into a server-owned slot at admission (the caller may reuse it once
+                                wf_poll has reported completion) */
+  const void* input;
+  int64_t ld_input;          /* elements, >= n */
+} wf_request;
+
+typedef struct wf_result {
+  const void* out;           /* device, server-owned; FULL mode: m x n with stride ld_out; else NULL */
+  int64_t ld_out;
+  const void* last_row;      /* device, server-owned, n values */
+  const void* last_col;      /* device, server-owned, m values */
+  const void* final_cell;    /* device, server-owned, 1 value */
+  double t_submit;           /* seconds on the server's monotonic clock */
+  double t_admit;
+  double t_launch;
+  double t_done;             /* time the server observed completion */
+} wf_result;
+
+/* Start a server thread that admits requests as device memory frees up,
+ * batches the admitted ones into persistent launches on up to max_inflight
+ * streams, and records completion times. */
+wf_status wf_server_create(wf_ctx* ctx, const wf_server_opts* opts, wf_server** out);
+/* Queue a request; never blocks on the GPU.  WF_E2BIG if it can never fit. */
+wf_status wf_submit(wf_server* s, const wf_request* r, uint64_t* ticket);
+/* WF_OK with *out filled when done, WF_PENDING before that. */
+wf_status wf_poll(wf_server* s, uint64_t ticket, wf_result* out);
+/* Free the request's slots; pointers from wf_poll become invalid. */
+wf_status wf_release(wf_server* s, uint64_t ticket);
+/* Drain admitted work, cancel the rest (WF_ESHUTDOWN), join the thread, free everything. */
+wf_status wf_server_destroy(wf_server* s);
+/* Bytes of device memory currently held for requests, and the peak so far. */
+wf_status wf_server_memory(wf_server* s, int64_t* in_use, int64_t* peak);
+
+/* ----------------------------------------------------------------- errors */
+const char* wf_last_error(void);
+const char* wf_status_str(wf_status s);
+/* Library version string. */
+const char* wf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WF_H */

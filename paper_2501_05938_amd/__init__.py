@@ -1,0 +1,236 @@
+"""Python binding of libwf, the MI355X (gfx950) anti-diagonal wavefront sweep.
+
+Only argument marshalling lives here: every step of the sweep runs in the HIP
+kernels of libwf.so (built in-tree by ``paper_2501_05938_amd.build``).  PyTorch
+tensors provide device memory and streams.  There is no CPU fallback: if the
+library is missing or the device is not gfx950, calls raise.
+
+    import torch, paper_2501_05938_amd as wf
+    H = wf.solve(cost)                       # cost: (m, n) float32/int32 CUDA tensor
+    last_row, last_col, final = wf.solve(cost, mode="edges")
+    outs = wf.solve_batched([c0, c1, ...])
+
+The cell rule (see include/wf.h): H[i][j] = c[i][j] + op(H[i-1][j], H[i][j-1], H[i-1][j-1]),
+op = min or max, with default or explicit top (n+1 values) / left (m values) boundaries.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwf.so")
+
+WF_OK, WF_PENDING = 0, 1
+STATUS = {0: "WF_OK", 1: "WF_PENDING", -1: "WF_EINVAL", -2: "WF_ENOMEM", -3: "WF_E2BIG", -4: "WF_EHIP",
+          -5: "WF_ETIMEDOUT", -6: "WF_ENOTFOUND", -7: "WF_ESHUTDOWN", -8: "WF_EUNSUPPORTED"}
+DTYPES = {"f32": 0, "i32": 1}
+RULES = {"min": 0, "max": 1}
+MODES = {"full": 0, "edges": 1}
+
+
+class WfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("dtype", ctypes.c_int32), ("rule", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("flags", ctypes.c_int32),
+                ("cost", ctypes.c_void_p), ("ld_cost", ctypes.c_int64),
+                ("out", ctypes.c_void_p), ("ld_out", ctypes.c_int64),
+                ("top", ctypes.c_void_p), ("left", ctypes.c_void_p),
+                ("last_row", ctypes.c_void_p), ("last_col", ctypes.c_void_p), ("final_cell", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("waves_per_wg", ctypes.c_int32), ("max_wgs", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("dtype", ctypes.c_int32), ("rule", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("input_kind", ctypes.c_int32), ("input", ctypes.c_void_p), ("ld_input", ctypes.c_int64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("out", ctypes.c_void_p), ("ld_out", ctypes.c_int64),
+                ("last_row", ctypes.c_void_p), ("last_col", ctypes.c_void_p), ("final_cell", ctypes.c_void_p),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+# Every symbol the C header declares, with its ctypes signature.
+_P = ctypes.c_void_p
+_SIGS = {
+    "wf_init": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_P)]),
+    "wf_destroy": (ctypes.c_int, [_P]),
+    "wf_solve": (ctypes.c_int, [_P, ctypes.POINTER(Problem), _P]),
+    "wf_solve_batched": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.c_int64, ctypes.POINTER(Tuning), _P]),
+    "wf_check": (ctypes.c_int, [_P]),
+    "wf_server_create": (ctypes.c_int, [_P, ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)]),
+    "wf_submit": (ctypes.c_int, [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "wf_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(Result)]),
+    "wf_release": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "wf_server_destroy": (ctypes.c_int, [_P]),
+    "wf_server_memory": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "wf_last_error": (ctypes.c_char_p, []),
+    "wf_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "wf_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libwf.so and bind every exported entry point (no GPU needed)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(path):
+                raise RuntimeError(f"libwf.so not built ({path}); run python -m paper_2501_05938_amd.build")
+            lib = ctypes.CDLL(path)
+            for name, (res, args) in _SIGS.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != WF_OK:
+        raise WfError(status, load_library().wf_last_error().decode(errors="replace"))
+
+
+_ctx = {}
+
+
+def context(device: int | None = None):
+    """The per-(thread, device) libwf context."""
+    import torch
+    if device is None:
+        device = torch.cuda.current_device()
+    key = (threading.get_ident(), device)
+    c = _ctx.get(key)
+    if c is None:
+        lib = load_library()
+        h = _P()
+        _check(lib.wf_init(device, ctypes.byref(h)))
+        c = _ctx[key] = h
+    return c
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dtype_of(t):
+    import torch
+    if t.dtype == torch.float32:
+        return "f32"
+    if t.dtype == torch.int32:
+        return "i32"
+    raise TypeError("cost must be float32 or int32")
+
+
+def _ld(t, n):
+    if t.dim() != 2 or t.stride(1) != 1 or t.stride(0) < n:
+        raise ValueError("expected a 2-D tensor with unit column stride and row stride >= n")
+    return t.stride(0)
+
+
+def make_problem(cost, out=None, rule="min", top=None, left=None, mode="full",
+                 last_row=None, last_col=None, final_cell=None) -> Problem:
+    """Fill a wf_problem from tensors (no allocation, no launch)."""
+    m, n = cost.shape
+    dt = _dtype_of(cost)
+    p = Problem()
+    p.m, p.n = m, n
+    p.dtype, p.rule, p.mode, p.flags = DTYPES[dt], RULES[rule], MODES[mode], 0
+    p.cost, p.ld_cost = cost.data_ptr(), _ld(cost, n)
+    if out is not None:
+        p.out, p.ld_out = out.data_ptr(), _ld(out, n)
+    for name, t, ln in (("top", top, n + 1), ("left", left, m)):
+        if t is not None:
+            if t.dtype != cost.dtype or t.dim() != 1 or t.numel() != ln or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous vector of {ln} {cost.dtype}")
+            setattr(p, name, t.data_ptr())
+    for name, t in (("last_row", last_row), ("last_col", last_col), ("final_cell", final_cell)):
+        if t is not None:
+            setattr(p, name, t.data_ptr())
+    return p
+
+
+def solve(cost, out=None, rule: str = "min", top=None, left=None, mode: str = "full", stream=None,
+          last_row=None, last_col=None, final_cell=None):
+    """Sweep one grid on the GPU (asynchronous on `stream`, default: current stream).
+
+    mode="full": returns H (m x n), written into `out` if given.
+    mode="edges": returns (last_row, last_col, final_cell) tensors.
+    """
+    import torch
+    if not cost.is_cuda:
+        raise ValueError("cost must be a device tensor")
+    m, n = cost.shape
+    if mode == "full" and out is None:
+        out = torch.empty((m, n), dtype=cost.dtype, device=cost.device)
+    if mode == "edges":
+        if last_row is None:
+            last_row = torch.empty(n, dtype=cost.dtype, device=cost.device)
+        if last_col is None:
+            last_col = torch.empty(m, dtype=cost.dtype, device=cost.device)
+        if final_cell is None:
+            final_cell = torch.empty(1, dtype=cost.dtype, device=cost.device)
+    p = make_problem(cost, out, rule, top, left, mode, last_row, last_col, final_cell)
+    _check(load_library().wf_solve(context(cost.device.index), ctypes.byref(p), _stream_ptr(stream)))
+    if mode == "full":
+        return out
+    return last_row, last_col, final_cell
+
+
+def solve_batched(costs, outs=None, rule: str = "min", mode: str = "full", stream=None,
+                  waves_per_wg: int = 0, max_wgs: int = 0, order: int = 0, use_graph: int = 1):
+    """Sweep many independent grids in one persistent launch.  Returns the list of outputs
+    (H per grid in full mode, (last_row, last_col, final_cell) in edges mode)."""
+    import torch
+    if outs is None:
+        outs = []
+        for c in costs:
+            m, n = c.shape
+            if mode == "full":
+                outs.append(torch.empty((m, n), dtype=c.dtype, device=c.device))
+            else:
+                outs.append((torch.empty(n, dtype=c.dtype, device=c.device),
+                             torch.empty(m, dtype=c.dtype, device=c.device),
+                             torch.empty(1, dtype=c.dtype, device=c.device)))
+    arr = (Problem * len(costs))()
+    for i, c in enumerate(costs):
+        if mode == "full":
+            arr[i] = make_problem(c, outs[i], rule, mode=mode)
+        else:
+            lr, lc, fc = outs[i]
+            arr[i] = make_problem(c, None, rule, mode=mode, last_row=lr, last_col=lc, final_cell=fc)
+    t = Tuning()
+    t.waves_per_wg, t.max_wgs, t.order, t.use_graph = waves_per_wg, max_wgs, order, use_graph
+    dev = costs[0].device.index if costs else None
+    _check(load_library().wf_solve_batched(context(dev), arr, len(costs), ctypes.byref(t), _stream_ptr(stream)))
+    return outs
+
+
+def check(device: int | None = None):
+    """Wait for the context's work; raise WfError if a device watchdog fired."""
+    _check(load_library().wf_check(context(device)))

@@ -1,0 +1,63 @@
+// Internal declarations shared by the kernel and runtime translation units of
+// libwf (not part of the public ABI; see include/wf.h for that).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wfk {
+
+// Device copy of one problem.  `hand` holds the bottom-row handoff of every
+// band but the last: band b writes row b, band b+1 reads it.
+struct GridDesc {
+  const void* cost;
+  void* out;
+  const void* top;
+  const void* left;
+  void* last_row;
+  void* last_col;
+  void* final_cell;
+  uint32_t* hand;
+  int64_t m, n, ld_cost, ld_out, hand_ld;
+  int32_t mode, nbands;
+};
+
+// One work item: band `band` of grid `grid`.
+struct Item {
+  uint32_t grid, band;
+};
+
+struct KArgs {
+  GridDesc g0;            // the grid when `grids` is null (single-grid launch)
+  const GridDesc* grids;  // batched: descriptor table
+  const Item* items;      // batched: work list in ticket order
+  int64_t nitems;
+  uint32_t* ctl;          // [0] ticket counter, [1] error code, [2] abort flag
+  uint64_t watchdog_ticks;
+};
+
+// Control-word indices.
+enum { CTL_TICKET = 0, CTL_ERROR = 1, CTL_ABORT = 2, CTL_WORDS = 4 };
+// Device error codes written to ctl[CTL_ERROR].
+enum { DEV_OK = 0, DEV_TIMEOUT = 1 };
+
+// Handoff sentinels ("not written yet"): a NaN pattern for fp32, INT32_MIN for int32.
+constexpr uint32_t SENT_F32 = 0xFFFFFFFFu;
+constexpr uint32_t SENT_I32 = 0x80000000u;
+
+// Rows per compute wave and positions per handoff row slack.
+constexpr int ROWS_PER_WAVE = 64;
+
+// Number of groups of 4 steps a 64-row strip of an n-column grid takes.
+__host__ __device__ inline int64_t groups_for(int64_t n) { return (n + 63 + 3) / 4; }
+// Handoff row length in positions (>= 4 * groups_for(n)).
+__host__ __device__ inline int64_t hand_ld_for(int64_t n) { return ((4 * groups_for(n)) + 63) / 64 * 64; }
+
+// Launch helpers implemented in wf_kernel.hip.
+// dtype 0 = f32, 1 = i32; rule 0 = min, 1 = max; W compute waves per workgroup.
+hipError_t launch_sweep(int dtype, int rule, int W, int nwg, const KArgs& args, hipStream_t stream);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t stream);
+// LDS bytes per workgroup for W compute waves (for occupancy decisions).
+size_t lds_bytes(int W);
+
+}  // namespace wfk

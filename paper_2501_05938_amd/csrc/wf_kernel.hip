@@ -1,0 +1,669 @@
+// wf_kernel.hip -- the persistent anti-diagonal wavefront sweep for gfx950.
+//
+// Cell rule (see include/wf.h): H[i][j] = c[i][j] + op(H[i-1][j], H[i][j-1], H[i-1][j-1]).
+//
+// Work decomposition
+//   A grid is cut into bands of 64*W rows.  A workgroup holds W "compute"
+//   waves (64 rows each, lane r owns row r) and W "IO" waves (IO wave w
+//   serves compute wave w).  Workgroups are persistent: they take band
+//   tickets from a global counter in order, so a band only ever waits on a
+//   band with a smaller ticket, which is held by a running workgroup.
+//
+// Compute wave (the hot loop)
+//   Lane r handles column t - r at step t, so each step advances a 64-cell
+//   anti-diagonal.  N comes from lane r-1 by a DPP wave_shr:1 of the previous
+//   step's H, NW is the previous step's N, W is the lane's own previous H.
+//   Lane 0's N is the bottom row of the strip above: it is supplied as the
+//   DPP "old" value, which a disabled source lane leaves in place.  Per step:
+//   one DPP move, one min3/max3, one add (a single rounding).
+//   Inputs c come from an LDS ring filled by the IO wave, stored skewed
+//   (row r, position p holds column p - r) so that all lanes read the same
+//   position with one aligned 16-byte load per 4 steps; H goes to a second
+//   LDS ring in the same layout.  Rows are padded by 16 bytes so the 64
+//   lanes' 16-byte accesses spread over the LDS banks.
+//
+// Handoff of the bottom row (the N of the next strip's lane 0)
+//   Inside a workgroup, lane 63 of compute wave w writes its 4 values of each
+//   step group into the T ring of wave w+1 (LDS).  Across workgroups, the last
+//   compute wave writes them to a global handoff row with device-coherent
+//   (sc1) stores, and IO wave 0 of the next band copies them into its T ring.
+//   Validity is carried by the data itself: slots hold a sentinel until
+//   written, and a reader accepts a quad only when none of its four words is
+//   the sentinel (a 16-byte read racing a 16-byte write may see part of it).  Consumers re-arm slots to the sentinel after
+//   use and publish how far they have re-armed; a producer writes a slot, and
+//   a consumer reads ahead into it, only once the slot's previous lap has been
+//   re-armed, so a stale value can never pass for a fresh one.
+//
+// IO wave
+//   Prefetches c into registers several chunks ahead (coalesced 16-byte rows),
+//   commits chunks into the c ring as the compute wave frees slots, stores
+//   finished H chunks to HBM with 16-byte stores, re-arms T slots, and for
+//   wave 0 feeds the T ring from the top boundary or the global handoff.
+//
+// Every wait has a wall-clock watchdog; on expiry the workgroup raises a
+// device-wide abort flag and all waits end, so a kernel always drains.
+#include "wf_internal.h"
+
+namespace wfk {
+namespace {
+
+constexpr int RING = 64;                // positions held by the c and H rings
+constexpr int PITCH = RING * 4 + 16;    // bytes per ring row
+constexpr int CHUNK = 16;               // positions per IO chunk
+constexpr int RING_T = 128;             // positions held by the T ring
+constexpr int DEPTH = 4;                // IO prefetch depth, in chunks
+
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u4a4 __attribute__((ext_vector_type(4), aligned(4)));
+
+struct alignas(16) WaveLds {
+  unsigned char cring[64 * PITCH];
+  unsigned char hring[64 * PITCH];
+  uint32_t tring[RING_T];
+  uint32_t c_ready;   // chunks of c committed to cring (IO -> compute)
+  uint32_t h_done;    // positions of H stored out of hring (IO -> compute)
+  uint32_t progress;  // (signed) positions computed; T positions < progress + 64 validated (compute -> IO)
+  uint32_t t_reset;   // T positions below this are re-armed (IO -> producer); slots < t_reset + RING_T writable
+  uint32_t abort;     // workgroup abort flag (only lds[0].abort is used)
+  uint32_t pad[11];
+};
+
+#define CBAR() asm volatile("" ::: "memory")
+
+template <typename T> __device__ __forceinline__ uint32_t bits(T v) { return __builtin_bit_cast(uint32_t, v); }
+template <typename T> __device__ __forceinline__ T from_bits(uint32_t u) { return __builtin_bit_cast(T, u); }
+
+template <typename T> struct Num;
+template <> struct Num<float> {
+  static constexpr uint32_t SENT = SENT_F32;
+  // The fp32 sentinel is the largest 32-bit pattern, so a quad holds it iff its unsigned max does.
+  __device__ static uint32_t probe(u4 q) {
+    uint32_t t = q.x > q.y ? q.x : q.y;
+    t = t > q.z ? t : q.z;
+    return t > q.w ? t : q.w;
+  }
+  template <int RULE> __device__ static float absent() { return RULE == 0 ? __builtin_inff() : -__builtin_inff(); }
+  template <int RULE> __device__ static float op3(float a, float b, float c) {
+    if constexpr (RULE == 0) return __builtin_fminf(__builtin_fminf(a, b), c);
+    else return __builtin_fmaxf(__builtin_fmaxf(a, b), c);
+  }
+  __device__ static float add(float a, float b) { return a + b; }
+};
+template <> struct Num<int32_t> {
+  static constexpr uint32_t SENT = SENT_I32;
+  // The int32 sentinel is INT32_MIN, so a quad holds it iff its signed min does.
+  __device__ static uint32_t probe(u4 q) {
+    int32_t t = (int32_t)q.x < (int32_t)q.y ? (int32_t)q.x : (int32_t)q.y;
+    t = t < (int32_t)q.z ? t : (int32_t)q.z;
+    return (uint32_t)(t < (int32_t)q.w ? t : (int32_t)q.w);
+  }
+  template <int RULE> __device__ static int32_t absent() { return RULE == 0 ? INT32_MAX : INT32_MIN + 1; }
+  template <int RULE> __device__ static int32_t op3(int32_t a, int32_t b, int32_t c) {
+    if constexpr (RULE == 0) { int32_t t = a < b ? a : b; return t < c ? t : c; }
+    else { int32_t t = a > b ? a : b; return t > c ? t : c; }
+  }
+  __device__ static int32_t add(int32_t a, int32_t b) { return (int32_t)((uint32_t)a + (uint32_t)b); }
+};
+
+// N for every lane: lane r receives lane r-1's `src`; lane 0 keeps `old`.
+template <typename T> __device__ __forceinline__ T dpp_shr1(T old, T src) {
+  return from_bits<T>((uint32_t)__builtin_amdgcn_update_dpp((int)bits(old), (int)bits(src), 0x138, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ uint32_t ld_ctl(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void st_ctl(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+typedef __attribute__((address_space(3))) unsigned char lds_u8;
+typedef __attribute__((address_space(3))) u4 lds_u4;
+template <class P> __device__ __forceinline__ lds_u8* L8(P* p) { return (lds_u8*)(void*)p; }
+__device__ __forceinline__ u4 lds_ld4(const lds_u8* p) { return *(const lds_u4*)p; }
+__device__ __forceinline__ u4 lds_ld4_fresh(const lds_u8* p) { return *(const volatile lds_u4*)p; }
+__device__ __forceinline__ void lds_st4(lds_u8* p, u4 v) { *(lds_u4*)p = v; }
+
+// Buffer descriptor for a wave-uniform base; forced into scalar registers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  const uint64_t b = (uint64_t)base;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  void* p = (void*)(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+constexpr int CPOL_SC1 = 16;  // device-scope coherent access
+
+typedef __attribute__((address_space(1))) uint32_t glb_u32;
+__device__ __forceinline__ glb_u32* G32(uint32_t* p) { return (glb_u32*)(void*)p; }
+__device__ __forceinline__ uint32_t ld_dev(uint32_t* p) {
+  return __hip_atomic_load(G32(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Abort the whole launch: raise the workgroup flag and the device-wide flag.
+__device__ __forceinline__ void raise_abort(WaveLds* lds, const KArgs& a) {
+  st_ctl(&lds[0].abort, 1u);
+  __hip_atomic_store(G32(a.ctl + CTL_ERROR), (uint32_t)DEV_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(G32(a.ctl + CTL_ABORT), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Spin until cond() holds.  Returns false (without waiting further) if the launch is
+// aborting; callers then run on to the end of the band, whose output is discarded.
+// Compute waves watch only the workgroup flag (no global loads on their path, so the
+// hot loop never waits on vector-memory counters); IO waves also poll the device flag
+// and relay it into the workgroup flag.
+template <bool DEVICE_FLAG, class F>
+__device__ __forceinline__ bool wait_until(F&& cond, WaveLds* lds, const KArgs& a) {
+  if (cond()) return true;
+  const uint64_t t0 = wall_clock64();
+  uint32_t polls = 0;
+  for (;;) {
+    __builtin_amdgcn_s_sleep(1);
+    if (cond()) return true;
+    if (ld_ctl(&lds[0].abort)) return false;
+    if (DEVICE_FLAG && (++polls & 255u) == 0u && ld_dev(a.ctl + CTL_ABORT)) {
+      st_ctl(&lds[0].abort, 1u);
+      return false;
+    }
+    if (wall_clock64() - t0 > a.watchdog_ticks) { raise_abort(lds, a); return false; }
+  }
+}
+
+// ------------------------------------------------------------ compute wave
+// Check for a launch abort (workgroup flag, then occasionally the device flag).
+__device__ __forceinline__ bool aborting(WaveLds* lds, uint32_t* ctl, uint64_t watchdog_ticks, uint32_t spins) {
+  if (ld_ctl(&lds[0].abort)) return true;
+  // s_sleep 1 is 64 clocks; the spin count bounds the wait to roughly watchdog_ticks.
+  if ((uint64_t)spins * 64u > watchdog_ticks * 24u) {
+    st_ctl(&lds[0].abort, 1u);
+    __hip_atomic_store(G32(ctl + CTL_ERROR), (uint32_t)DEV_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(G32(ctl + CTL_ABORT), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+  }
+  return false;
+}
+
+// Spin until the T quad at `tp` has been written.  Returns false if the launch is aborting.
+template <typename T>
+__device__ __noinline__ u4 wait_quad(const lds_u8* tp, WaveLds* lds, uint32_t* ctl, uint64_t watchdog_ticks) {
+  uint32_t spins = 0;
+  u4 q;
+  do {
+    __builtin_amdgcn_s_sleep(1);
+    q = lds_ld4_fresh(tp);
+    if ((++spins & 1023u) == 0u && aborting(lds, ctl, watchdog_ticks, spins)) break;
+  } while (Num<T>::probe(q) == Num<T>::SENT);
+  return q;
+}
+
+// One chunk (4 groups of 4 steps) of the walk.
+// KIND 0: the first four chunks, where lanes left of column 0 keep their boundary value
+//         and bounds are checked;  KIND 1: interior, no bounds checks;  KIND 2: tail.
+// CONS: 0 = no consumer, 1 = the next compute wave (LDS), 2 = the next band (global).
+template <typename T, int RULE, int KIND, int CONS>
+__device__ __forceinline__ void compute_chunk(
+    int k, int G, int gT, int NCc, WaveLds* lds, WaveLds& L, WaveLds* C,
+    __amdgpu_buffer_rsrc_t hand_out, lds_u8* crow, lds_u8* hrow, lds_u8* ct_base, bool lane63, int lane,
+    u4 (&cq)[4], u4 (&tq)[4], uint32_t& tprev_w, T& H, T& Np, const KArgs& a) {
+  const uint32_t SENT = Num<T>::SENT;
+  const int pos = CHUNK * k;
+  // Chunk start: publish progress, then wait until the c ring holds this chunk and the next
+  // (reads run two groups ahead), the H slots are free, and the consumer's T slots are re-armed.
+  CBAR();
+  if (lane == 0) st_ctl(&L.progress, (uint32_t)pos);
+  {
+    const int need_c = k + 2 < NCc ? k + 2 : NCc;
+    const int need_h = pos + CHUNK - RING;
+    const int need_t = pos + CHUNK - RING_T;
+    // This chunk reads T quads up to position pos + CHUNK + 8 + 64 (two groups ahead);
+    // their slots must no longer hold the previous lap's values.
+    const int need_own_t = pos + CHUNK + 8 + 64 - RING_T;
+    wait_until<false>([&] {
+      if ((int)ld_ctl(&L.c_ready) < need_c) return false;
+      if ((int)ld_ctl(&L.h_done) < need_h) return false;
+      if ((int)ld_ctl(&L.t_reset) < need_own_t) return false;
+      if (CONS == 1 && (int)ld_ctl(&C->t_reset) < need_t) return false;
+      return true;
+    }, lds, a);
+  }
+  CBAR();
+  lds_u8* cb = crow + (k & 3) * (CHUNK * 4);
+  lds_u8* cb_next = crow + ((k + 1) & 3) * (CHUNK * 4);
+  lds_u8* hb = hrow + (k & 3) * (CHUNK * 4);
+  const lds_u8* tr_base = L8(L.tring);
+  const int tpos = (pos + 64) & (RING_T - 1);             // T ring position of group 4k's quad
+  const int tpos_next = (pos + CHUNK + 64) & (RING_T - 1);
+  lds_u8* ct = ct_base + (pos & (RING_T - 1)) * 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int g = 4 * k + q;
+    if (KIND == 2 && g >= G) break;
+    // 1. LDS reads of group g+2 (a read past the end only picks up unused stale data).
+    const int g2 = g + 2;
+    cq[(q + 2) & 3] = lds_ld4(q + 2 < 4 ? cb + 16 * (q + 2) : cb_next + 16 * (q - 2));
+    if (KIND == 1 || g2 < gT)
+      tq[(q + 2) & 3] = lds_ld4(tr_base + (q + 2 < 4 ? tpos + 4 * (q + 2) : tpos_next + 4 * (q - 2)) * 4);
+    // 2. The T quad of this group must have been written by the producer.
+    if (KIND == 1 || g < gT) {
+      // All four words are checked: a 16-byte LDS read racing a 16-byte write from another
+      // wave may see part of it.  All lanes read the same quad, so the test is wave-uniform.
+      if (__builtin_expect(__builtin_amdgcn_readfirstlane(Num<T>::probe(tq[q])) == SENT, 0))
+        tq[q] = wait_quad<T>(tr_base + (tpos + 4 * q) * 4, lds, a.ctl, a.watchdog_ticks);
+    }
+    // 3. Four steps of the anti-diagonal walk.
+    const u4 cv = cq[q];
+    const u4 tv = tq[q];
+    const uint32_t tk[4] = {tprev_w, tv.x, tv.y, tv.z};
+    if (KIND == 1 || g < gT) tprev_w = tv.w;
+    u4 h4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const T N = dpp_shr1<T>(from_bits<T>(tk[e]), H);
+      T Hn = Num<T>::add(from_bits<T>(cv[e]), Num<T>::template op3<RULE>(N, Np, H));
+      if (KIND == 0) Hn = (4 * g + e < lane) ? H : Hn;  // lanes left of column 0 keep the left boundary
+      Np = N;
+      H = Hn;
+      h4[e] = bits(H);
+    }
+    // 4. H into the ring, bottom row to the consumer.  Positions < 60 are never read by a consumer.
+    lds_st4(hb + 16 * q, h4);
+    if (CONS != 0 && (KIND != 0 || g >= 15)) {
+      if (lane63) {
+        if (CONS == 1) lds_st4(ct + 16 * q, h4);
+        else __builtin_amdgcn_raw_buffer_store_b128(h4, hand_out, 16 * g, 0, CPOL_SC1);
+      }
+    }
+  }
+}
+
+template <typename T, int RULE, int CONS>
+__device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLds& L, WaveLds* C, __amdgpu_buffer_rsrc_t hand_out,
+                             lds_u8* crow, lds_u8* hrow, int lane, T H, const KArgs& a) {
+  const int NCc = (4 * G + CHUNK - 1) / CHUNK;
+  lds_u8* ct_base = CONS == 1 ? L8(C->tring) : nullptr;
+  const bool lane63 = lane == 63;
+  // First T quad: positions 60..63 = columns -3..0 of the row above (.z is the corner, .w column 0).
+  u4 tprev = lds_ld4_fresh(L8(L.tring) + 60 * 4);
+  if (Num<T>::probe(tprev) == Num<T>::SENT) tprev = wait_quad<T>(L8(L.tring) + 60 * 4, lds, a.ctl, a.watchdog_ticks);
+  T Np = from_bits<T>(tprev.z);
+  uint32_t tprev_w = tprev.w;
+  u4 cq[4], tq[4];
+  wait_until<false>([&] { return ld_ctl(&L.c_ready) >= 1u; }, lds, a);
+  CBAR();
+  cq[0] = lds_ld4(crow + 0);
+  cq[1] = lds_ld4(crow + 16);
+  cq[2] = cq[3] = cq[0];
+  tq[0] = lds_ld4(L8(L.tring) + 64 * 4);
+  tq[1] = lds_ld4(L8(L.tring) + 68 * 4);
+  tq[2] = tq[3] = tprev;
+
+  int k = 0;
+  for (; k < 4; ++k)
+    compute_chunk<T, RULE, 0, CONS>(k, G, gT, NCc, lds, L, C, hand_out, crow, hrow, ct_base, lane63, lane,
+                                    cq, tq, tprev_w, H, Np, a);
+  for (; 4 * k + 6 <= gT; ++k)
+    compute_chunk<T, RULE, 1, CONS>(k, G, gT, NCc, lds, L, C, hand_out, crow, hrow, ct_base, lane63, lane,
+                                    cq, tq, tprev_w, H, Np, a);
+  for (; k < NCc; ++k)
+    compute_chunk<T, RULE, 2, CONS>(k, G, gT, NCc, lds, L, C, hand_out, crow, hrow, ct_base, lane63, lane,
+                                    cq, tq, tprev_w, H, Np, a);
+  CBAR();
+  if (lane == 0) st_ctl(&L.progress, (uint32_t)(4 * G));
+}
+
+template <typename T, int RULE, int W>
+__device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLds* lds, int w, int lane, const KArgs& a) {
+  WaveLds& L = lds[w];
+  const int64_t m = g.m, n = g.n;
+  const int64_t row0 = (int64_t)band * (64 * W) + 64 * w;
+  if (row0 >= m) return;
+  const int G = (int)groups_for(n);
+  const int gT = n >= 2 ? (int)((n - 2) / 4 + 1) : 0;
+  const bool lds_consumer = (w + 1 < W && row0 + 64 < m);
+  const bool glob_consumer = (w == W - 1) && (band + 1 < g.nbands);
+  const int64_t row = row0 + lane;
+  T H = Num<T>::template absent<RULE>();
+  if (g.left && row < m) H = ((const T*)g.left)[row];
+  lds_u8* crow = L8(L.cring) + lane * PITCH;
+  lds_u8* hrow = L8(L.hring) + lane * PITCH;
+  if (lds_consumer) {
+    compute_walk<T, RULE, 1>(G, gT, lds, L, &lds[w + 1], __amdgpu_buffer_rsrc_t(), crow, hrow, lane, H, a);
+  } else if (glob_consumer) {
+    __amdgpu_buffer_rsrc_t hand_out = make_rsrc(g.hand + (int64_t)band * g.hand_ld, (uint32_t)(g.hand_ld * 4));
+    compute_walk<T, RULE, 2>(G, gT, lds, L, nullptr, hand_out, crow, hrow, lane, H, a);
+  } else {
+    compute_walk<T, RULE, 0>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), crow, hrow, lane, H, a);
+  }
+}
+
+// ----------------------------------------------------------------- IO wave
+template <typename T>
+struct IoBand {
+  const GridDesc* g;
+  int band, w, lane;
+  int G, NC, T_END;
+  int64_t m, n, row0;
+  bool full;
+};
+
+__device__ __forceinline__ uint32_t pick(const u4& v, int e) {
+  return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
+}
+
+// Load chunk k of c for this wave's 64 rows into registers (4 x 16 bytes per lane).
+// Lane mapping of load i: row rho = 16 i + lane/4, positions 16k + 4(lane%4) .. +3.
+template <typename T>
+__device__ __forceinline__ void io_load_chunk(const IoBand<T>& B, const uint32_t* const (&rp)[4], int k, u4 (&dst)[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rho = 16 * i + (B.lane >> 2);
+    const int64_t col = 16 * k + 4 * (B.lane & 3) - rho;
+    if (col >= 0 && col + 3 <= B.n - 1) {
+      dst[i] = *(const u4a4*)(rp[i] + col);
+    } else {
+      u4 v;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int64_t cc = col + e;
+        cc = cc < 0 ? 0 : (cc > B.n - 1 ? B.n - 1 : cc);
+        v[e] = rp[i][cc];
+      }
+      dst[i] = v;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void io_commit_chunk(const IoBand<T>& B, WaveLds& L, int k, const u4 (&src)[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rho = 16 * i + (B.lane >> 2);
+    lds_st4(L8(L.cring) + rho * PITCH + ((16 * k + 4 * (B.lane & 3)) & (RING - 1)) * 4, src[i]);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void io_store_chunk(const IoBand<T>& B, WaveLds& L, int k) {
+  const GridDesc& g = *B.g;
+  u4 v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rho = 16 * i + (B.lane >> 2);
+    v[i] = lds_ld4(L8(L.hring) + rho * PITCH + ((16 * k + 4 * (B.lane & 3)) & (RING - 1)) * 4);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rho = 16 * i + (B.lane >> 2);
+    const int64_t row = B.row0 + rho;
+    const int64_t col = 16 * k + 4 * (B.lane & 3) - rho;
+    if (row >= B.m || col > B.n - 1 || col + 3 < 0) continue;
+    if (B.full) {
+      uint32_t* op = (uint32_t*)g.out + row * g.ld_out;
+      if (col >= 0 && col + 3 <= B.n - 1) {
+        *(u4a4*)(op + col) = v[i];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (col + e >= 0 && col + e <= B.n - 1) op[col + e] = pick(v[i], e);
+      }
+    }
+    const bool has_last = col <= B.n - 1 && col + 3 >= B.n - 1;
+    if (has_last && g.last_col) ((uint32_t*)g.last_col)[row] = pick(v[i], (int)(B.n - 1 - col));
+    if (row == B.m - 1) {
+      if (g.last_row) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (col + e >= 0 && col + e <= B.n - 1) ((uint32_t*)g.last_row)[col + e] = pick(v[i], e);
+      }
+      if (has_last && g.final_cell) *(uint32_t*)g.final_cell = pick(v[i], (int)(B.n - 1 - col));
+    }
+  }
+}
+
+// Feed the T ring of compute wave 0 with up to 16 quads starting at position tw.
+// Returns the number of positions written.
+template <typename T, int RULE>
+__device__ __forceinline__ int io_feed_t(const IoBand<T>& B, WaveLds& L, int tw, int limit, __amdgpu_buffer_rsrc_t hand_in) {
+  const uint32_t SENT = Num<T>::SENT;
+  const int nq = (limit - tw) / 4;
+  const int p = tw + 4 * B.lane;
+  const bool mine = B.lane < nq && B.lane < 16;
+  u4 v = {SENT, SENT, SENT, SENT};
+  bool valid = false;
+  if (mine) {
+    if (B.band == 0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t ti = (int64_t)p + e - 62;  // index into top[] (= column + 1)
+        T val = Num<T>::template absent<RULE>();
+        if (ti >= 0 && ti <= B.n) {
+          if (B.g->top) val = ((const T*)B.g->top)[ti];
+          else if (ti == 0) val = (T)0;
+        }
+        v[e] = bits(val);
+      }
+      valid = true;
+    } else {
+      v = __builtin_amdgcn_raw_buffer_load_b128(hand_in, p * 4, 0, CPOL_SC1);
+      valid = v.x != SENT && v.y != SENT && v.z != SENT && v.w != SENT;
+    }
+  }
+  const uint64_t ok = __builtin_amdgcn_ballot_w64(valid);
+  const int nvalid = (int)__builtin_ctzll(~ok);  // leading run of valid quads
+  if (nvalid > 0 && B.lane < nvalid) {
+    lds_st4(L8(L.tring) + (p & (RING_T - 1)) * 4, v);
+    if (B.band != 0) {
+      u4 s4 = {SENT, SENT, SENT, SENT};
+      __builtin_amdgcn_raw_buffer_store_b128(s4, hand_in, p * 4, 0, 0);
+    }
+  }
+  return 4 * nvalid;
+}
+
+template <typename T, int RULE, int W>
+__device__ __forceinline__ void io_band(const GridDesc& g, int band, WaveLds* lds, int w, int lane, const KArgs& a) {
+  WaveLds& L = lds[w];
+  IoBand<T> B;
+  B.g = &g;
+  B.band = band;
+  B.w = w;
+  B.lane = lane;
+  B.m = g.m;
+  B.n = g.n;
+  B.row0 = (int64_t)band * (64 * W) + 64 * w;
+  if (B.row0 >= B.m) return;
+  B.G = (int)groups_for(g.n);
+  B.NC = (4 * B.G + CHUNK - 1) / CHUNK;
+  B.T_END = 4 * B.G;
+  B.full = g.mode == 0;
+  const uint32_t SENT = Num<T>::SENT;
+  __amdgpu_buffer_rsrc_t hand_in =
+      make_rsrc(g.hand + (band > 0 ? (int64_t)(band - 1) * g.hand_ld : 0), (uint32_t)(g.hand_ld * 4));
+  const uint32_t* rp[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int64_t row = B.row0 + 16 * i + (lane >> 2);
+    if (row > B.m - 1) row = B.m - 1;
+    rp[i] = (const uint32_t*)g.cost + row * g.ld_cost;
+  }
+
+  u4 rr[DEPTH][4];
+#pragma unroll
+  for (int d = 0; d < DEPTH; ++d)
+    if (d < B.NC) io_load_chunk<T>(B, rp, d, rr[d]);
+
+  int kc = 0;       // next chunk to commit to the c ring
+  int ks = 0;       // next chunk to store out
+  int tr = 60;      // T positions re-armed
+  int tw = w == 0 ? 60 : B.T_END;  // next T position to feed (wave 0 only)
+  uint64_t t_idle = wall_clock64();
+  uint32_t polls = 0;
+  for (;;) {
+    bool did = false;
+    const int prog = (int)ld_ctl(&L.progress);
+    CBAR();
+    // Commit chunk kc once the compute wave has read the chunk that used its slot.
+    if (kc < B.NC && prog >= 16 * (kc - 3)) {
+      switch (kc % DEPTH) {
+#define WF_COMMIT_CASE(d)                                                   \
+  case d:                                                                   \
+    io_commit_chunk<T>(B, L, kc, rr[d]);                                    \
+    if (kc + DEPTH < B.NC) io_load_chunk<T>(B, rp, kc + DEPTH, rr[d]);      \
+    break;
+        WF_COMMIT_CASE(0) WF_COMMIT_CASE(1) WF_COMMIT_CASE(2) WF_COMMIT_CASE(3)
+#undef WF_COMMIT_CASE
+      }
+      ++kc;
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+      CBAR();
+      if (lane == 0) st_ctl(&L.c_ready, (uint32_t)kc);
+      did = true;
+    }
+    // Store out finished H chunks (the last chunk ends at 4G, which need not be a multiple of 16).
+    if (ks < B.NC && prog >= (16 * (ks + 1) < B.T_END ? 16 * (ks + 1) : B.T_END)) {
+      io_store_chunk<T>(B, L, ks);
+      ++ks;
+      __builtin_amdgcn_s_waitcnt(0xc07f);
+      CBAR();
+      if (lane == 0) st_ctl(&L.h_done, (uint32_t)(16 * ks));
+      did = true;
+    }
+    // Re-arm T slots the compute wave has validated (positions < progress + 64).
+    {
+      int target = prog + 64;
+      if (target > B.T_END) target = B.T_END;
+      if (target > tr) {
+        const int nq = (target - tr) / 4;
+        for (int base = 0; base < nq; base += 64) {
+          if (base + lane < nq) {
+            const int p = tr + 4 * (base + lane);
+            u4 s4 = {SENT, SENT, SENT, SENT};
+            lds_st4(L8(L.tring) + (p & (RING_T - 1)) * 4, s4);
+          }
+        }
+        tr = target;
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        CBAR();
+        if (lane == 0) st_ctl(&L.t_reset, (uint32_t)tr);
+        did = true;
+      }
+    }
+    // Wave 0 feeds its T ring from the top boundary or from the band above.
+    if (tw < B.T_END) {
+      int limit = tr + RING_T;
+      if (limit > B.T_END) limit = B.T_END;
+      if (tw < limit) {
+        const int got = io_feed_t<T, RULE>(B, L, tw, limit, hand_in);
+        if (got > 0) {
+          tw += got;
+          did = true;
+        }
+      }
+    }
+    if (ks >= B.NC && tr >= B.T_END && tw >= B.T_END) break;
+    if (did) {
+      t_idle = wall_clock64();
+      continue;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    if (ld_ctl(&lds[0].abort)) return;
+    if ((++polls & 255u) == 0u && ld_dev(a.ctl + CTL_ABORT)) {
+      st_ctl(&lds[0].abort, 1u);
+      return;
+    }
+    if (wall_clock64() - t_idle > a.watchdog_ticks) {
+      raise_abort(lds, a);
+      return;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ kernel
+// Two waves per SIMD (one compute, one IO) whatever W is, so at most 256 VGPRs.
+template <typename T, int RULE, int W>
+__global__ __attribute__((amdgpu_flat_work_group_size(128 * W, 128 * W), amdgpu_waves_per_eu(2, 2)))
+void wf_sweep_kernel(KArgs a) {
+  __shared__ WaveLds lds[W];
+  __shared__ uint32_t s_item;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      uint32_t t = atomicAdd(&a.ctl[CTL_TICKET], 1u);
+      if (ld_dev(a.ctl + CTL_ABORT)) t = 0xFFFFFFFFu;
+      s_item = t;
+    }
+    // Re-arm this workgroup's LDS state for the next band.
+    if (wave < W) {
+      WaveLds& L = lds[wave];
+      const uint32_t SENT = Num<T>::SENT;
+      for (int i = lane; i < RING_T; i += 64) L.tring[i] = SENT;
+      if (lane == 0) {
+        L.c_ready = 0;
+        L.h_done = 0;
+        // -16: nothing computed and no T quad validated yet.  The compute wave publishes 0
+        // only after it has validated the first quad (positions 60..63), so the IO wave
+        // cannot re-arm or refill that slot before it has been read.
+        L.progress = (uint32_t)-16;
+        L.t_reset = 60;
+        L.abort = 0;
+      }
+    }
+    __syncthreads();
+    const uint32_t t = __builtin_amdgcn_readfirstlane(s_item);
+    if ((int64_t)t >= a.nitems) break;
+    GridDesc gd;
+    int band;
+    if (a.grids) {
+      const Item it = a.items[t];
+      gd = a.grids[it.grid];
+      band = (int)it.band;
+    } else {
+      gd = a.g0;
+      band = (int)t;
+    }
+    if (wave < W) compute_band<T, RULE, W>(gd, band, lds, wave, lane, a);
+    else io_band<T, RULE, W>(gd, band, lds, wave - W, lane, a);
+    __syncthreads();
+  }
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
+}
+
+template <typename T, int RULE, int W>
+hipError_t launch_t(int nwg, const KArgs& args, hipStream_t stream) {
+  hipLaunchKernelGGL((wf_sweep_kernel<T, RULE, W>), dim3(nwg), dim3(128 * W), 0, stream, args);
+  return hipGetLastError();
+}
+
+template <typename T, int RULE>
+hipError_t launch_w(int W, int nwg, const KArgs& args, hipStream_t stream) {
+  switch (W) {
+    case 1: return launch_t<T, RULE, 1>(nwg, args, stream);
+    case 2: return launch_t<T, RULE, 2>(nwg, args, stream);
+    case 4: return launch_t<T, RULE, 4>(nwg, args, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+size_t lds_bytes(int W) { return sizeof(WaveLds) * (size_t)W + 16; }
+
+hipError_t launch_sweep(int dtype, int rule, int W, int nwg, const KArgs& args, hipStream_t stream) {
+  if (dtype == 0) return rule == 0 ? launch_w<float, 0>(W, nwg, args, stream) : launch_w<float, 1>(W, nwg, args, stream);
+  if (dtype == 1) return rule == 0 ? launch_w<int32_t, 0>(W, nwg, args, stream) : launch_w<int32_t, 1>(W, nwg, args, stream);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, value, count);
+  return hipGetLastError();
+}
+
+}  // namespace wfk

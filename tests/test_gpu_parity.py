@@ -1,0 +1,171 @@
+"""GPU parity: the HIP sweep (through the C ABI) against the CPU oracle, element
+by element, on seeded inputs.
+
+Bar: bit-exact for fp32 against the fp32 oracle loop (the result of
+"one rounding after an exact min/max" does not depend on evaluation order) and
+bit-exact for int32; against the fp64 oracle every cell must satisfy
+|H32 - H64| <= gamma_{i+j+1} * |H64| (the rounding bound pinned in
+test_oracle_pins.py).  Shapes cover one row/column, several bands of every
+workgroup size (64, 128 and 256 rows), ragged tails and leading dimensions
+larger than n.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_2501_05938_amd as wf  # noqa: E402
+import wfgen  # noqa: E402
+
+U = 2.0 ** -24
+DEV = torch.device("cuda:0")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _gamma_bound(H64):
+    m, n = H64.shape
+    k = (np.arange(m)[:, None] + np.arange(n)[None, :] + 1).astype(np.float64)
+    return k * U / (1 - k * U) * np.abs(H64)
+
+
+def _case(m, n, rule="min", dtype="f32", seed=1, explicit=False, ld_pad=0):
+    print(f"[parity] m={m} n={n} rule={rule} dtype={dtype} seed={seed} explicit={explicit} ld_pad={ld_pad}",
+          flush=True)
+    c = wfgen.cells(seed, m, n, dtype)
+    top = left = None
+    if explicit:
+        top = (wfgen.vector(seed + 100, n + 1, dtype) * (3 if dtype == "f32" else 2)).astype(c.dtype)
+        left = (wfgen.vector(seed + 200, m, dtype) * (3 if dtype == "f32" else 2)).astype(c.dtype)
+    if ld_pad:
+        cb = np.zeros((m, n + ld_pad), c.dtype)
+        cb[:, :n] = c
+        cd = _dev(cb)[:, :n]
+        out = torch.full((m, n + ld_pad), float("nan") if dtype == "f32" else -7, dtype=cd.dtype, device=DEV)[:, :n]
+    else:
+        cd = _dev(c)
+        out = torch.full((m, n), float("nan") if dtype == "f32" else -7, dtype=cd.dtype, device=DEV)
+    H = wf.solve(cd, out=out, rule=rule, top=None if top is None else _dev(top),
+                 left=None if left is None else _dev(left))
+    got = _host(H)
+    wf.check()
+    if dtype == "f32":
+        exp32 = oracle.sweep(c, rule, "f32", top=top, left=left)
+        bad = np.argwhere(got.view(np.uint32) != exp32.view(np.uint32))
+        assert bad.size == 0, f"{len(bad)} cells differ; first {bad[:5].tolist()} got {got[tuple(bad[0])]} want {exp32[tuple(bad[0])]}"
+        exp64 = oracle.sweep(c, rule, "f64", top=None if top is None else top.astype(np.float64),
+                             left=None if left is None else left.astype(np.float64))
+        assert (np.abs(got.astype(np.float64) - exp64) <= _gamma_bound(exp64)).all()
+    else:
+        exp = oracle.sweep(c, rule, "i64", top=None if top is None else top.astype(np.int64),
+                           left=None if left is None else left.astype(np.int64))
+        assert np.array_equal(got.astype(np.int64), exp)
+    return got
+
+
+SMALL = [(1, 1), (1, 2), (2, 1), (1, 100), (100, 1), (3, 5), (5, 3), (63, 63), (64, 64), (65, 65),
+         (64, 1000), (100, 37), (37, 100), (128, 128), (129, 300)]
+MEDIUM = [(256, 256), (300, 513), (511, 700), (512, 512), (700, 129), (1024, 1024)]
+TALL = [(2047, 100), (2048, 77), (2100, 333), (4097, 65), (64, 4099)]
+
+
+@pytest.mark.parametrize("m,n", SMALL)
+def test_small_shapes_f32_min(m, n):
+    _case(m, n)
+
+
+@pytest.mark.parametrize("m,n", MEDIUM + TALL)
+def test_banded_shapes_f32_min(m, n):
+    _case(m, n, seed=2)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (65, 65), (300, 513), (2100, 333)])
+def test_max_rule(m, n):
+    _case(m, n, rule="max", seed=3)
+
+
+@pytest.mark.parametrize("m,n", [(1, 7), (65, 65), (300, 513), (2100, 333)])
+@pytest.mark.parametrize("rule", ["min", "max"])
+def test_int32(m, n, rule):
+    _case(m, n, rule=rule, dtype="i32", seed=4)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (7, 9), (129, 300), (2100, 333)])
+@pytest.mark.parametrize("dtype", ["f32", "i32"])
+def test_explicit_boundary(m, n, dtype):
+    _case(m, n, dtype=dtype, seed=5, explicit=True)
+    _case(m, n, rule="max", dtype=dtype, seed=6, explicit=True)
+
+
+@pytest.mark.parametrize("m,n", [(65, 65), (600, 1000)])
+def test_leading_dimension(m, n):
+    _case(m, n, seed=7, ld_pad=13)
+
+
+def test_config_small_grid_1024_and_repeatability():
+    """The 1024 x 1024 configuration, twice, bit-identical both times."""
+    a = _case(1024, 1024, seed=1)
+    b = _case(1024, 1024, seed=1)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (70, 300), (2100, 333)])
+def test_edges_mode(m, n):
+    print(f"[edges] m={m} n={n}", flush=True)
+    c = wfgen.cells(8, m, n, "f32")
+    lr, lc, fc = wf.solve(_dev(c), mode="edges")
+    exp = oracle.sweep(c, "min", "f32")
+    assert np.array_equal(_host(lr).view(np.uint32), exp[-1].view(np.uint32))
+    assert np.array_equal(_host(lc).view(np.uint32), exp[:, -1].view(np.uint32))
+    assert _host(fc)[0] == exp[-1, -1]
+
+
+def test_device_fill_matches_host_generator():
+    for dtype, tdt in (("f32", torch.float32), ("i32", torch.int32)):
+        t = torch.empty((300, 517), dtype=tdt, device=DEV)
+        wfgen.fill_device(t, seed=123, row0=40)
+        exp = wfgen.cells(123, 340, 517, dtype, 40, 300)
+        assert np.array_equal(_host(t), exp)
+
+
+def test_empty_grid_is_a_no_op():
+    c = torch.empty((0, 5), dtype=torch.float32, device=DEV)
+    out = wf.solve(c)
+    assert out.shape == (0, 5)
+
+
+@pytest.mark.slow
+def test_full_size_16384_against_fp32_oracle():
+    """The 16384 x 16384 configuration, launched as the benchmark launches it:
+    device-filled input, whole output compared bit-exactly with the fp32 oracle."""
+    m = n = 16384
+    print("[parity] 16384^2 full grid", flush=True)
+    cd = torch.empty((m, n), dtype=torch.float32, device=DEV)
+    wfgen.fill_device(cd, seed=2)
+    H = wf.solve(cd)
+    got = _host(H)
+    wf.check()
+    c = wfgen.cells(2, m, n, "f32")
+    exp = oracle.sweep(c, "min", "f32")
+    bad = np.count_nonzero(got.view(np.uint32) != exp.view(np.uint32))
+    assert bad == 0, f"{bad} cells differ"
+    rows = [0, 1, n // 2, m - 2, m - 1] + list(np.random.default_rng(2).integers(0, m, 16))
+    exp64 = oracle.sweep(c, "min", "f64")
+    for r in rows:
+        k = (r + np.arange(n) + 1).astype(np.float64)
+        assert (np.abs(got[r].astype(np.float64) - exp64[r]) <= k * U / (1 - k * U) * exp64[r]).all()

@@ -92,3 +92,52 @@ def serving_requests(count: int, rate_per_s: float, lo: int = 128, hi: int = 819
     u = rng.uniform(math.log(lo), math.log(hi + 1), size=count)
     ns = np.clip(np.floor(np.exp(u)).astype(np.int64), lo, hi)
     return [(float(a), int(b), 50000 + q) for q, (a, b) in enumerate(zip(t, ns))]
+
+
+# ------------------------------------------------------------- device fill
+import ctypes as _ctypes
+import os as _os
+import subprocess as _subprocess
+
+_HERE = _os.path.dirname(_os.path.abspath(__file__))
+_FILL_SRC = _os.path.join(_HERE, "wfgen_fill.hip")
+FILL_LIB = _os.path.join(_HERE, "libwfgen.so")
+_fill_lib = None
+
+
+def build_fill(force: bool = True) -> str:
+    """Compile libwfgen.so (the device-side fill) for gfx950."""
+    if force or not _os.path.exists(FILL_LIB):
+        cmd = ["/opt/rocm/bin/hipcc", "-O3", "-fPIC", "-shared", "--offload-arch=gfx950",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-o", FILL_LIB + ".tmp", _FILL_SRC]
+        _subprocess.run(cmd, check=True, stderr=_subprocess.DEVNULL)
+        _os.replace(FILL_LIB + ".tmp", FILL_LIB)
+    return FILL_LIB
+
+
+def fill_device(t, seed: int, row0: int = 0, n_cols: int | None = None, stream=None):
+    """Fill a 2-D device tensor (rows x n, unit column stride) with the same values
+    cells(seed, ..., row0, rows) would give, for a grid of n_cols columns (default n)."""
+    import torch
+    global _fill_lib
+    if _fill_lib is None:
+        if not _os.path.exists(FILL_LIB):
+            raise RuntimeError("libwfgen.so not built; call wfgen.build_fill()")
+        lib = _ctypes.CDLL(FILL_LIB)
+        lib.wfgen_fill.restype = _ctypes.c_int
+        lib.wfgen_fill.argtypes = [_ctypes.c_void_p, _ctypes.c_int, _ctypes.c_int64, _ctypes.c_int64,
+                                   _ctypes.c_int64, _ctypes.c_uint64, _ctypes.c_int64, _ctypes.c_void_p]
+        _fill_lib = lib
+    rows, n = t.shape
+    if n_cols is not None and n_cols != n:
+        raise ValueError("a band must span the full grid width")
+    if t.stride(1) != 1:
+        raise ValueError("unit column stride required")
+    dt = {torch.float32: 0, torch.int32: 1}[t.dtype]
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = _fill_lib.wfgen_fill(t.data_ptr(), dt, rows, n, t.stride(0), seed & 0xFFFFFFFFFFFFFFFF, row0,
+                              s.cuda_stream)
+    if rc != 0:
+        raise RuntimeError(f"wfgen_fill failed with HIP error {rc}")
+    return t
