@@ -34,7 +34,16 @@ struct KArgs {
   int64_t nitems;
   uint32_t* ctl;          // [0] ticket counter, [1] error code, [2] abort flag
   uint64_t watchdog_ticks;
+  uint64_t* trace;        // optional: TRACE_WORDS per (work item, compute wave), see below
 };
+
+// Per (work item, compute wave) trace record, written when KArgs::trace is set:
+//   [0] grid << 32 | band << 8 | wave      [1] clock at band start (s_memtime)
+//   [2] clock when the first top-boundary quad was valid   [3] clock at band end
+//   [4] cycles waiting at chunk starts (c ring, H ring, T ring capacity)
+//   [5] cycles waiting for top-boundary quads   [6] loader cycles waiting for a free c slot
+//   [7] wall clock (100 MHz) at band start
+constexpr int TRACE_WORDS = 8;
 
 // Control-word indices.
 enum { CTL_TICKET = 0, CTL_ERROR = 1, CTL_ABORT = 2, CTL_WORDS = 4 };

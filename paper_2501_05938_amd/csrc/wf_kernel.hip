@@ -3,11 +3,12 @@
 // Cell rule (see include/wf.h): H[i][j] = c[i][j] + op(H[i-1][j], H[i][j-1], H[i-1][j-1]).
 //
 // Work decomposition
-//   A grid is cut into bands of 64*W rows.  A workgroup holds W "compute"
-//   waves (64 rows each, lane r owns row r) and W "IO" waves (IO wave w
-//   serves compute wave w).  Workgroups are persistent: they take band
-//   tickets from a global counter in order, so a band only ever waits on a
-//   band with a smaller ticket, which is held by a running workgroup.
+//   A grid is cut into bands of 64*W rows.  Workgroups are persistent: they
+//   take band tickets from a global counter in order, so a band only ever
+//   waits on a band with a smaller ticket, which is held by a running
+//   workgroup.  A workgroup holds W compute waves (64 rows each, lane r owns
+//   row r) and staging waves that never mix load and store traffic: one
+//   loader per compute wave, one storer per two compute waves and one feeder.
 //
 // Compute wave (the hot loop)
 //   Lane r handles column t - r at step t, so each step advances a 64-cell
@@ -16,29 +17,26 @@
 //   Lane 0's N is the bottom row of the strip above: it is supplied as the
 //   DPP "old" value, which a disabled source lane leaves in place.  Per step:
 //   one DPP move, one min3/max3, one add (a single rounding).
-//   Inputs c come from an LDS ring filled by the IO wave, stored skewed
+//   Inputs c come from an LDS ring filled by the loader, stored skewed
 //   (row r, position p holds column p - r) so that all lanes read the same
 //   position with one aligned 16-byte load per 4 steps; H goes to a second
 //   LDS ring in the same layout.  Rows are padded by 16 bytes so the 64
-//   lanes' 16-byte accesses spread over the LDS banks.
+//   lanes' 16-byte accesses spread over the LDS banks.  The compute wave
+//   issues no vector-memory loads, so it never waits on memory counters.
 //
 // Handoff of the bottom row (the N of the next strip's lane 0)
 //   Inside a workgroup, lane 63 of compute wave w writes its 4 values of each
 //   step group into the T ring of wave w+1 (LDS).  Across workgroups, the last
 //   compute wave writes them to a global handoff row with device-coherent
-//   (sc1) stores, and IO wave 0 of the next band copies them into its T ring.
+//   (sc1) stores, and the feeder of the next band copies them into the T ring
+//   of its compute wave 0.
 //   Validity is carried by the data itself: slots hold a sentinel until
 //   written, and a reader accepts a quad only when none of its four words is
-//   the sentinel (a 16-byte read racing a 16-byte write may see part of it).  Consumers re-arm slots to the sentinel after
-//   use and publish how far they have re-armed; a producer writes a slot, and
-//   a consumer reads ahead into it, only once the slot's previous lap has been
-//   re-armed, so a stale value can never pass for a fresh one.
-//
-// IO wave
-//   Prefetches c into registers several chunks ahead (coalesced 16-byte rows),
-//   commits chunks into the c ring as the compute wave frees slots, stores
-//   finished H chunks to HBM with 16-byte stores, re-arms T slots, and for
-//   wave 0 feeds the T ring from the top boundary or the global handoff.
+//   the sentinel (a 16-byte read racing a 16-byte write may see part of it).
+//   Consumers re-arm slots to the sentinel after use and publish how far they
+//   have re-armed; a producer writes a slot, and a consumer reads ahead into
+//   it, only once the slot's previous lap has been re-armed, so a stale value
+//   can never pass for a fresh one.
 //
 // Every wait has a wall-clock watchdog; on expiry the workgroup raises a
 // device-wide abort flag and all waits end, so a kernel always drains.
@@ -47,25 +45,39 @@
 namespace wfk {
 namespace {
 
-constexpr int RING = 64;                // positions held by the c and H rings
-constexpr int PITCH = RING * 4 + 16;    // bytes per ring row
 constexpr int CHUNK = 16;               // positions per IO chunk
+constexpr int SLOT = 64 * CHUNK * 4;    // bytes of one chunk slot (64 rows x 16 positions)
+constexpr int C_SLOTS = 6;              // chunk slots of the c ring
+constexpr int H_SLOTS = 3;              // chunk slots of the H ring
 constexpr int RING_T = 128;             // positions held by the T ring
-constexpr int DEPTH = 4;                // IO prefetch depth, in chunks
+// Inside a slot, the 16 bytes of row r, quad q (positions 4q..4q+3 of the chunk)
+// sit at (r/16)*1024 + q*256 + (r%16)*16: for one quad, 16 consecutive rows are
+// 256 contiguous bytes, so a wave's 16-byte accesses to one quad never share a
+// bank cycle, and a 64-lane LDS-DMA load (lane L -> byte 16L) fills one quad of
+// 16 rows in each of four 1024-byte blocks.
+constexpr int QUAD = 256;
+__device__ __forceinline__ int lane_off(int r) { return (r >> 4) * 1024 + (r & 15) * 16; }
 
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u4a4 __attribute__((ext_vector_type(4), aligned(4)));
 
 struct alignas(16) WaveLds {
-  unsigned char cring[64 * PITCH];
-  unsigned char hring[64 * PITCH];
+  unsigned char cring[C_SLOTS * SLOT];
+  unsigned char hring[H_SLOTS * SLOT];
   uint32_t tring[RING_T];
   uint32_t c_ready;   // chunks of c committed to cring (IO -> compute)
   uint32_t h_done;    // positions of H stored out of hring (IO -> compute)
   uint32_t progress;  // (signed) positions computed; T positions < progress + 64 validated (compute -> IO)
   uint32_t t_reset;   // T positions below this are re-armed (IO -> producer); slots < t_reset + RING_T writable
   uint32_t abort;     // workgroup abort flag (only lds[0].abort is used)
-  uint32_t pad[11];
+  uint32_t t_fed;     // wave 0: T positions copied into the ring by the feeder (feeder -> storer)
+  uint32_t pad[2];
+  // trace counters (written only when KArgs::trace is set)
+  uint64_t tr_start, tr_first, tr_end, tr_wall;
+  uint64_t tr_chunk_wait;   // compute cycles waiting at chunk starts
+  uint64_t tr_t_wait;       // compute cycles waiting for T quads
+  uint64_t tr_load_wait;    // loader cycles waiting for a free c slot
+  uint64_t tr_pad;
 };
 
 #define CBAR() asm volatile("" ::: "memory")
@@ -182,16 +194,32 @@ __device__ __forceinline__ bool aborting(WaveLds* lds, uint32_t* ctl, uint64_t w
   return false;
 }
 
+// Called every few thousand spins of an inline wait: true when the wait should end
+// (launch aborting, or no progress for longer than the watchdog since t0).
+__device__ __noinline__ bool spin_expired(WaveLds* lds, uint32_t* ctl, uint64_t watchdog_ticks, uint64_t t0) {
+  if (ld_ctl(&lds[0].abort)) return true;
+  if (wall_clock64() - t0 > watchdog_ticks) {
+    st_ctl(&lds[0].abort, 1u);
+    __hip_atomic_store(G32(ctl + CTL_ERROR), (uint32_t)DEV_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(G32(ctl + CTL_ABORT), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+  }
+  return false;
+}
+
 // Spin until the T quad at `tp` has been written.  Returns false if the launch is aborting.
 template <typename T>
-__device__ __noinline__ u4 wait_quad(const lds_u8* tp, WaveLds* lds, uint32_t* ctl, uint64_t watchdog_ticks) {
+__device__ __noinline__ u4 wait_quad(const lds_u8* tp, WaveLds* lds, uint32_t* ctl, uint64_t watchdog_ticks,
+                                     uint64_t* wait_acc) {
   uint32_t spins = 0;
+  const uint64_t c0 = wait_acc ? __builtin_readcyclecounter() : 0;
   u4 q;
   do {
     __builtin_amdgcn_s_sleep(1);
     q = lds_ld4_fresh(tp);
     if ((++spins & 1023u) == 0u && aborting(lds, ctl, watchdog_ticks, spins)) break;
   } while (Num<T>::probe(q) == Num<T>::SENT);
+  if (wait_acc) *wait_acc += __builtin_readcyclecounter() - c0;
   return q;
 }
 
@@ -212,23 +240,29 @@ __device__ __forceinline__ void compute_chunk(
   if (lane == 0) st_ctl(&L.progress, (uint32_t)pos);
   {
     const int need_c = k + 2 < NCc ? k + 2 : NCc;
-    const int need_h = pos + CHUNK - RING;
+    const int need_h = pos + CHUNK - H_SLOTS * CHUNK;
     const int need_t = pos + CHUNK - RING_T;
     // This chunk reads T quads up to position pos + CHUNK + 8 + 64 (two groups ahead);
     // their slots must no longer hold the previous lap's values.
     const int need_own_t = pos + CHUNK + 8 + 64 - RING_T;
-    wait_until<false>([&] {
+    auto ready = [&] {
       if ((int)ld_ctl(&L.c_ready) < need_c) return false;
       if ((int)ld_ctl(&L.h_done) < need_h) return false;
       if ((int)ld_ctl(&L.t_reset) < need_own_t) return false;
       if (CONS == 1 && (int)ld_ctl(&C->t_reset) < need_t) return false;
       return true;
-    }, lds, a);
+    };
+    if (!ready()) {
+      const uint64_t c0 = __builtin_readcyclecounter();
+      wait_until<false>(ready, lds, a);
+      if (a.trace && lane == 0) L.tr_chunk_wait += __builtin_readcyclecounter() - c0;
+    }
   }
   CBAR();
-  lds_u8* cb = crow + (k & 3) * (CHUNK * 4);
-  lds_u8* cb_next = crow + ((k + 1) & 3) * (CHUNK * 4);
-  lds_u8* hb = hrow + (k & 3) * (CHUNK * 4);
+  const int cs = k % C_SLOTS;
+  lds_u8* cb = crow + cs * SLOT;
+  lds_u8* cb_next = crow + (cs + 1 == C_SLOTS ? 0 : cs + 1) * SLOT;
+  lds_u8* hb = hrow + (k % H_SLOTS) * SLOT;
   const lds_u8* tr_base = L8(L.tring);
   const int tpos = (pos + 64) & (RING_T - 1);             // T ring position of group 4k's quad
   const int tpos_next = (pos + CHUNK + 64) & (RING_T - 1);
@@ -239,15 +273,33 @@ __device__ __forceinline__ void compute_chunk(
     if (KIND == 2 && g >= G) break;
     // 1. LDS reads of group g+2 (a read past the end only picks up unused stale data).
     const int g2 = g + 2;
-    cq[(q + 2) & 3] = lds_ld4(q + 2 < 4 ? cb + 16 * (q + 2) : cb_next + 16 * (q - 2));
+    cq[(q + 2) & 3] = lds_ld4(q + 2 < 4 ? cb + QUAD * (q + 2) : cb_next + QUAD * (q - 2));
     if (KIND == 1 || g2 < gT)
       tq[(q + 2) & 3] = lds_ld4(tr_base + (q + 2 < 4 ? tpos + 4 * (q + 2) : tpos_next + 4 * (q - 2)) * 4);
     // 2. The T quad of this group must have been written by the producer.
     if (KIND == 1 || g < gT) {
       // All four words are checked: a 16-byte LDS read racing a 16-byte write from another
       // wave may see part of it.  All lanes read the same quad, so the test is wave-uniform.
-      if (__builtin_expect(__builtin_amdgcn_readfirstlane(Num<T>::probe(tq[q])) == SENT, 0))
-        tq[q] = wait_quad<T>(tr_base + (tpos + 4 * q) * 4, lds, a.ctl, a.watchdog_ticks);
+      if (__builtin_expect(__builtin_amdgcn_readfirstlane(Num<T>::probe(tq[q])) == SENT, 0)) {
+        // Miss: the producer is just ahead.  Wait for the NEXT quad as well, which leaves one
+        // group of slack so the following checks hit; the producer writes in order, so once
+        // quad g+1 is complete quad g is too.  Both are re-read.
+        const lds_u8* tp = tr_base + (tpos + 4 * q) * 4;
+        const lds_u8* tp1 = tr_base + (q + 1 < 4 ? tpos + 4 * (q + 1) : tpos_next + 4 * (q - 3)) * 4;
+        const bool ahead = KIND == 1 || g + 1 < gT;
+        const lds_u8* tw = ahead ? tp1 : tp;
+        const uint64_t c0 = a.trace ? __builtin_readcyclecounter() : 0;
+        const uint64_t t0 = wall_clock64();
+        uint32_t spins = 0;
+        u4 probe_q;
+        do {
+          probe_q = lds_ld4_fresh(tw);
+          if ((++spins & 2047u) == 0u && spin_expired(lds, a.ctl, a.watchdog_ticks, t0)) break;
+        } while (__builtin_amdgcn_readfirstlane(Num<T>::probe(probe_q)) == SENT);
+        tq[q] = lds_ld4_fresh(tp);
+        if (ahead) tq[(q + 1) & 3] = lds_ld4_fresh(tp1);
+        if (a.trace && lane == 0) L.tr_t_wait += __builtin_readcyclecounter() - c0;
+      }
     }
     // 3. Four steps of the anti-diagonal walk.
     const u4 cv = cq[q];
@@ -265,7 +317,7 @@ __device__ __forceinline__ void compute_chunk(
       h4[e] = bits(H);
     }
     // 4. H into the ring, bottom row to the consumer.  Positions < 60 are never read by a consumer.
-    lds_st4(hb + 16 * q, h4);
+    lds_st4(hb + QUAD * q, h4);
     if (CONS != 0 && (KIND != 0 || g >= 15)) {
       if (lane63) {
         if (CONS == 1) lds_st4(ct + 16 * q, h4);
@@ -283,14 +335,16 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   const bool lane63 = lane == 63;
   // First T quad: positions 60..63 = columns -3..0 of the row above (.z is the corner, .w column 0).
   u4 tprev = lds_ld4_fresh(L8(L.tring) + 60 * 4);
-  if (Num<T>::probe(tprev) == Num<T>::SENT) tprev = wait_quad<T>(L8(L.tring) + 60 * 4, lds, a.ctl, a.watchdog_ticks);
+  if (Num<T>::probe(tprev) == Num<T>::SENT)
+    tprev = wait_quad<T>(L8(L.tring) + 60 * 4, lds, a.ctl, a.watchdog_ticks, nullptr);
+  if (a.trace && lane == 0) L.tr_first = __builtin_readcyclecounter();
   T Np = from_bits<T>(tprev.z);
   uint32_t tprev_w = tprev.w;
   u4 cq[4], tq[4];
   wait_until<false>([&] { return ld_ctl(&L.c_ready) >= 1u; }, lds, a);
   CBAR();
   cq[0] = lds_ld4(crow + 0);
-  cq[1] = lds_ld4(crow + 16);
+  cq[1] = lds_ld4(crow + QUAD);
   cq[2] = cq[3] = cq[0];
   tq[0] = lds_ld4(L8(L.tring) + 64 * 4);
   tq[1] = lds_ld4(L8(L.tring) + 68 * 4);
@@ -321,10 +375,14 @@ __device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLd
   const bool lds_consumer = (w + 1 < W && row0 + 64 < m);
   const bool glob_consumer = (w == W - 1) && (band + 1 < g.nbands);
   const int64_t row = row0 + lane;
+  if (a.trace && lane == 0) {
+    L.tr_start = __builtin_readcyclecounter();
+    L.tr_wall = wall_clock64();
+  }
   T H = Num<T>::template absent<RULE>();
   if (g.left && row < m) H = ((const T*)g.left)[row];
-  lds_u8* crow = L8(L.cring) + lane * PITCH;
-  lds_u8* hrow = L8(L.hring) + lane * PITCH;
+  lds_u8* crow = L8(L.cring) + lane_off(lane);
+  lds_u8* hrow = L8(L.hring) + lane_off(lane);
   if (lds_consumer) {
     compute_walk<T, RULE, 1>(G, gT, lds, L, &lds[w + 1], __amdgpu_buffer_rsrc_t(), crow, hrow, lane, H, a);
   } else if (glob_consumer) {
@@ -333,70 +391,204 @@ __device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLd
   } else {
     compute_walk<T, RULE, 0>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), crow, hrow, lane, H, a);
   }
+  if (a.trace && lane == 0) L.tr_end = __builtin_readcyclecounter();
 }
 
-// ----------------------------------------------------------------- IO wave
-template <typename T>
-struct IoBand {
-  const GridDesc* g;
-  int band, w, lane;
-  int G, NC, T_END;
-  int64_t m, n, row0;
-  bool full;
-};
+// ------------------------------------------------------------- IO waves
+// The staging work of compute wave w is split over waves that never mix load
+// and store traffic: on gfx9 the vector-memory counter does not return loads
+// and stores in order with respect to each other, so a wave holding both must
+// drain everything before it can use any loaded value.
+//   loader w : loads of c (register prefetch, DEPTH chunks ahead) -> c ring
+//   storer s : H stage-out, T-ring re-arming, handoff-row re-arming (stores only)
+//   feeder   : the T ring of compute wave 0, from the top boundary or from the
+//              band above (loads only)
 
 __device__ __forceinline__ uint32_t pick(const u4& v, int e) {
-  return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
+  return e <= 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
 }
 
-// Load chunk k of c for this wave's 64 rows into registers (4 x 16 bytes per lane).
-// Lane mapping of load i: row rho = 16 i + lane/4, positions 16k + 4(lane%4) .. +3.
-template <typename T>
-__device__ __forceinline__ void io_load_chunk(const IoBand<T>& B, const uint32_t* const (&rp)[4], int k, u4 (&dst)[4]) {
+struct BandGeom {
+  int64_t m, n, row0;
+  int G, NC, T_END;
+};
+
+template <int W>
+__device__ __forceinline__ BandGeom band_geom(const GridDesc& g, int band, int w) {
+  BandGeom b;
+  b.m = g.m;
+  b.n = g.n;
+  b.row0 = (int64_t)band * (64 * W) + 64 * w;
+  b.G = (int)groups_for(g.n);
+  b.NC = (4 * b.G + CHUNK - 1) / CHUNK;
+  b.T_END = 4 * b.G;
+  return b;
+}
+
+// ------------------------------------------------------------- loader
+// Chunk k of c for the 64 rows of a strip goes straight from memory into c-ring
+// slot k % C_SLOTS with LDS-DMA loads (buffer_load_dwordx4 ... lds): load i
+// covers rows 16i .. 16i+15, lane L reading row 16i + L%16 at positions
+// 16k + 4(L/16) .. +3, i.e. columns col .. col+3 with col = 16k + 4(L/16) - row.
+// The hardware writes lane L's 16 bytes at M0 + 16L, which is the slot layout.
+//
+// Offsets are taken from a buffer descriptor based at the strip's first row
+// and ending at the grid's last element: quads left of a row's column 0 pick
+// up the end of the row above, quads right of column n-1 the start of the row
+// below (neither is ever used), and quads past the end of the grid are
+// range-checked by the hardware (no access).  A quad that straddles the end of
+// the grid and still holds columns of the row is rewritten with element loads.
+//
+// The loads are issued from inline assembly and waited for with explicit
+// vmcnt values: the loader issues nothing else on that counter while DMA loads
+// are in flight, and the compiler, which cannot see these loads, inserts no
+// waits of its own for them.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void dma_quad16(__amdgpu_buffer_rsrc_t rsrc, uint32_t voff, uint32_t lds_addr) {
+  // M0 holds the LDS destination; nothing else in this kernel uses M0.
+  asm volatile("s_mov_b32 m0, %2\n\tbuffer_load_dwordx4 %0, %1, 0 offen lds"
+               :: "v"(voff), "s"(rsrc), "s"(lds_addr) : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+// Wait until at most 4*younger DMA loads of this wave are outstanding.
+__device__ __forceinline__ void wait_dma(int younger) {
+  switch (younger) {
+    case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    case 1: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+    case 2: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
+    case 3: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
+    case 4: asm volatile("s_waitcnt vmcnt(16)" ::: "memory"); break;
+    default: asm volatile("s_waitcnt vmcnt(20)" ::: "memory"); break;
+  }
+}
+static_assert(C_SLOTS <= 6, "wait_dma covers at most 5 younger chunks");
+
+struct LoaderLanes {
+  int64_t rel[4];    // element offset of (row, column 16k' + 4(L/16) - row) for k' = 0, from the strip base
+  int rho[4];        // row inside the strip (not clamped)
+  bool real[4];      // the row exists
+};
+
+// Idle step of a polling IO wave: sleep, then check abort and the watchdog.
+// Only waves that may load from memory (DEVICE_FLAG) poll the device-wide flag;
+// the others watch the workgroup flag, which those relay.
+template <bool DEVICE_FLAG>
+__device__ __forceinline__ bool io_idle(WaveLds* lds, const KArgs& a, uint64_t& t_idle, uint32_t& polls) {
+  __builtin_amdgcn_s_sleep(1);
+  if (ld_ctl(&lds[0].abort)) return false;
+  if (DEVICE_FLAG && (++polls & 255u) == 0u && ld_dev(a.ctl + CTL_ABORT)) {
+    st_ctl(&lds[0].abort, 1u);
+    return false;
+  }
+  if (wall_clock64() - t_idle > a.watchdog_ticks) {
+    raise_abort(lds, a);
+    return false;
+  }
+  return true;
+}
+
+template <int W>
+__device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds* lds, int w, int lane,
+                                            const KArgs& a) {
+  const BandGeom B = band_geom<W>(g, band, w);
+  if (B.row0 >= B.m) return;
+  WaveLds& L = lds[w];
+  // Elements from the strip's first row to the end of the grid.
+  const int64_t span = (B.m - 1 - B.row0) * g.ld_cost + B.n;
+  const uint32_t span_bytes = (uint32_t)(span * 4 < 0xFFFFFFF0ll ? span * 4 : 0xFFFFFFF0ll);
+  const __amdgpu_buffer_rsrc_t rsrc = make_rsrc((const uint32_t*)g.cost + B.row0 * g.ld_cost, span_bytes);
+  const int64_t last_rho = B.m - 1 - B.row0;
+  LoaderLanes ln;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int rho = 16 * i + (B.lane >> 2);
-    const int64_t col = 16 * k + 4 * (B.lane & 3) - rho;
-    if (col >= 0 && col + 3 <= B.n - 1) {
-      dst[i] = *(const u4a4*)(rp[i] + col);
-    } else {
-      u4 v;
+    const int rho = 16 * i + (lane & 15);
+    const int64_t rr = rho < last_rho ? rho : last_rho;
+    ln.rho[i] = rho;
+    ln.real[i] = rho <= last_rho;
+    ln.rel[i] = rr * g.ld_cost + 4 * (lane >> 4) - rho;
+  }
+  const uint32_t slot0 = (uint32_t)(uintptr_t)L8(L.cring);
+  const int NC = B.NC;
+  int issued = 0, committed = 0;
+  uint64_t t_idle = wall_clock64();
+  uint32_t polls = 0;
+  for (;;) {
+    // Issue every chunk whose slot the compute wave has released: slot k % C_SLOTS
+    // last held chunk k - C_SLOTS, read completely once progress >= 16 (k - C_SLOTS + 1).
+    while (issued < NC && (int)ld_ctl(&L.progress) >= 16 * (issued - C_SLOTS + 1)) {
+      const uint32_t base = slot0 + (uint32_t)((issued % C_SLOTS) * SLOT);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int64_t cc = col + e;
-        cc = cc < 0 ? 0 : (cc > B.n - 1 ? B.n - 1 : cc);
-        v[e] = rp[i][cc];
+      for (int i = 0; i < 4; ++i) {
+        const int64_t e = ln.rel[i] + 16 * issued;  // element offset from the strip base
+        // Quads not wholly inside [strip base, end of grid) are not loaded at all (an
+        // out-of-range offset): rows past the end of a ragged strip and the grid's tail.
+        const uint32_t voff = (e < 0 || e + 4 > span) ? 0xFFFFFFFFu : (uint32_t)(e * 4);
+        dma_quad16(rsrc, voff, __builtin_amdgcn_readfirstlane(base + 1024u * i));
       }
-      dst[i] = v;
+      ++issued;
     }
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void io_commit_chunk(const IoBand<T>& B, WaveLds& L, int k, const u4 (&src)[4]) {
+    if (committed < issued) {
+      const int k = committed;
+      wait_dma(issued - committed - 1);
+      // Quads that straddle the end of the grid and hold columns of a real row.
+      bool fix[4];
+      bool any = false;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int rho = 16 * i + (B.lane >> 2);
-    lds_st4(L8(L.cring) + rho * PITCH + ((16 * k + 4 * (B.lane & 3)) & (RING - 1)) * 4, src[i]);
+      for (int i = 0; i < 4; ++i) {
+        const int64_t col = 16 * k + 4 * (lane >> 4) - ln.rho[i];
+        const int64_t e = ln.rel[i] + 16 * k;
+        fix[i] = ln.real[i] && e + 4 > span && col <= B.n - 1 && col + 3 >= 0;
+        any |= fix[i];
+      }
+      if (__builtin_amdgcn_ballot_w64(any)) {
+        typedef __attribute__((address_space(1))) const uint32_t g32;
+        const g32* cbase = (const g32*)(const void*)((const uint32_t*)g.cost + B.row0 * g.ld_cost);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (!fix[i]) continue;
+          const int64_t col = 16 * k + 4 * (lane >> 4) - ln.rho[i];
+          u4 v;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            v[e] = (col + e >= 0 && col + e <= B.n - 1) ? cbase[(int64_t)ln.rho[i] * g.ld_cost + col + e] : 0u;
+          lds_st4(L8(L.cring) + (k % C_SLOTS) * SLOT + 1024 * i + 16 * lane, v);
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+      }
+      CBAR();
+      if (lane == 0) st_ctl(&L.c_ready, (uint32_t)(k + 1));
+      ++committed;
+      t_idle = wall_clock64();
+      continue;
+    }
+    if (committed == NC) break;
+    const uint64_t c0 = a.trace ? __builtin_readcyclecounter() : 0;
+    bool ok = true;
+    while ((int)ld_ctl(&L.progress) < 16 * (issued - C_SLOTS + 1)) {
+      if (!(ok = io_idle<false>(lds, a, t_idle, polls))) break;
+    }
+    if (a.trace && lane == 0) L.tr_load_wait += __builtin_readcyclecounter() - c0;
+    if (!ok) break;
   }
+  wait_dma(0);  // nothing may still be writing the ring when the band ends
 }
 
-template <typename T>
-__device__ __forceinline__ void io_store_chunk(const IoBand<T>& B, WaveLds& L, int k) {
-  const GridDesc& g = *B.g;
+// Store chunk k of H (64 rows x 16 positions) from the H ring: lane L covers
+// row 16i + L%16, positions 16k + 4(L/16) .. +3 (contiguous LDS reads).
+__device__ __forceinline__ void store_chunk(const GridDesc& g, const BandGeom& B, WaveLds& L, int k, int lane) {
   u4 v[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int rho = 16 * i + (B.lane >> 2);
-    v[i] = lds_ld4(L8(L.hring) + rho * PITCH + ((16 * k + 4 * (B.lane & 3)) & (RING - 1)) * 4);
-  }
+  for (int i = 0; i < 4; ++i) v[i] = lds_ld4(L8(L.hring) + (k % H_SLOTS) * SLOT + 1024 * i + 16 * lane);
+  const bool full = g.mode == 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int rho = 16 * i + (B.lane >> 2);
+    const int rho = 16 * i + (lane & 15);
     const int64_t row = B.row0 + rho;
-    const int64_t col = 16 * k + 4 * (B.lane & 3) - rho;
+    const int64_t col = 16 * k + 4 * (lane >> 4) - rho;
     if (row >= B.m || col > B.n - 1 || col + 3 < 0) continue;
-    if (B.full) {
+    if (full) {
       uint32_t* op = (uint32_t*)g.out + row * g.ld_out;
       if (col >= 0 && col + 3 <= B.n - 1) {
         *(u4a4*)(op + col) = v[i];
@@ -419,168 +611,160 @@ __device__ __forceinline__ void io_store_chunk(const IoBand<T>& B, WaveLds& L, i
   }
 }
 
-// Feed the T ring of compute wave 0 with up to 16 quads starting at position tw.
-// Returns the number of positions written.
-template <typename T, int RULE>
-__device__ __forceinline__ int io_feed_t(const IoBand<T>& B, WaveLds& L, int tw, int limit, __amdgpu_buffer_rsrc_t hand_in) {
+// One storer serves compute waves 2s and 2s+1.
+template <typename T, int W>
+__device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds* lds, int s, int lane,
+                                            const KArgs& a) {
   const uint32_t SENT = Num<T>::SENT;
-  const int nq = (limit - tw) / 4;
-  const int p = tw + 4 * B.lane;
-  const bool mine = B.lane < nq && B.lane < 16;
-  u4 v = {SENT, SENT, SENT, SENT};
-  bool valid = false;
-  if (mine) {
-    if (B.band == 0) {
+  constexpr int PER = 2;
+  BandGeom B[PER];
+  bool active[PER];
+  int ks[PER], tr[PER];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t ti = (int64_t)p + e - 62;  // index into top[] (= column + 1)
-        T val = Num<T>::template absent<RULE>();
-        if (ti >= 0 && ti <= B.n) {
-          if (B.g->top) val = ((const T*)B.g->top)[ti];
-          else if (ti == 0) val = (T)0;
-        }
-        v[e] = bits(val);
-      }
-      valid = true;
-    } else {
-      v = __builtin_amdgcn_raw_buffer_load_b128(hand_in, p * 4, 0, CPOL_SC1);
-      valid = v.x != SENT && v.y != SENT && v.z != SENT && v.w != SENT;
-    }
+  for (int j = 0; j < PER; ++j) {
+    const int w = PER * s + j;
+    B[j] = band_geom<W>(g, band, w < W ? w : 0);
+    active[j] = w < W && B[j].row0 < B[j].m;
+    ks[j] = 0;
+    tr[j] = 60;
   }
-  const uint64_t ok = __builtin_amdgcn_ballot_w64(valid);
-  const int nvalid = (int)__builtin_ctzll(~ok);  // leading run of valid quads
-  if (nvalid > 0 && B.lane < nvalid) {
-    lds_st4(L8(L.tring) + (p & (RING_T - 1)) * 4, v);
-    if (B.band != 0) {
-      u4 s4 = {SENT, SENT, SENT, SENT};
-      __builtin_amdgcn_raw_buffer_store_b128(s4, hand_in, p * 4, 0, 0);
-    }
-  }
-  return 4 * nvalid;
-}
-
-template <typename T, int RULE, int W>
-__device__ __forceinline__ void io_band(const GridDesc& g, int band, WaveLds* lds, int w, int lane, const KArgs& a) {
-  WaveLds& L = lds[w];
-  IoBand<T> B;
-  B.g = &g;
-  B.band = band;
-  B.w = w;
-  B.lane = lane;
-  B.m = g.m;
-  B.n = g.n;
-  B.row0 = (int64_t)band * (64 * W) + 64 * w;
-  if (B.row0 >= B.m) return;
-  B.G = (int)groups_for(g.n);
-  B.NC = (4 * B.G + CHUNK - 1) / CHUNK;
-  B.T_END = 4 * B.G;
-  B.full = g.mode == 0;
-  const uint32_t SENT = Num<T>::SENT;
+  // Handoff-row re-arming: only the storer of compute wave 0, only below band 0.
+  const bool rearm_hand = s == 0 && band > 0;
   __amdgpu_buffer_rsrc_t hand_in =
       make_rsrc(g.hand + (band > 0 ? (int64_t)(band - 1) * g.hand_ld : 0), (uint32_t)(g.hand_ld * 4));
-  const uint32_t* rp[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int64_t row = B.row0 + 16 * i + (lane >> 2);
-    if (row > B.m - 1) row = B.m - 1;
-    rp[i] = (const uint32_t*)g.cost + row * g.ld_cost;
-  }
-
-  u4 rr[DEPTH][4];
-#pragma unroll
-  for (int d = 0; d < DEPTH; ++d)
-    if (d < B.NC) io_load_chunk<T>(B, rp, d, rr[d]);
-
-  int kc = 0;       // next chunk to commit to the c ring
-  int ks = 0;       // next chunk to store out
-  int tr = 60;      // T positions re-armed
-  int tw = w == 0 ? 60 : B.T_END;  // next T position to feed (wave 0 only)
+  int hr = 60;
+  const int hand_end = B[0].T_END;
   uint64_t t_idle = wall_clock64();
   uint32_t polls = 0;
   for (;;) {
-    bool did = false;
-    const int prog = (int)ld_ctl(&L.progress);
-    CBAR();
-    // Commit chunk kc once the compute wave has read the chunk that used its slot.
-    if (kc < B.NC && prog >= 16 * (kc - 3)) {
-      switch (kc % DEPTH) {
-#define WF_COMMIT_CASE(d)                                                   \
-  case d:                                                                   \
-    io_commit_chunk<T>(B, L, kc, rr[d]);                                    \
-    if (kc + DEPTH < B.NC) io_load_chunk<T>(B, rp, kc + DEPTH, rr[d]);      \
-    break;
-        WF_COMMIT_CASE(0) WF_COMMIT_CASE(1) WF_COMMIT_CASE(2) WF_COMMIT_CASE(3)
-#undef WF_COMMIT_CASE
+    bool did = false, done = true;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      if (!active[j]) continue;
+      WaveLds& L = lds[PER * s + j];
+      const int prog = (int)ld_ctl(&L.progress);
+      CBAR();
+      const int lim = 16 * (ks[j] + 1) < B[j].T_END ? 16 * (ks[j] + 1) : B[j].T_END;
+      if (ks[j] < B[j].NC && prog >= lim) {
+        store_chunk(g, B[j], L, ks[j], lane);
+        ++ks[j];
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // the ring reads are done before the slot is released
+        CBAR();
+        if (lane == 0) st_ctl(&L.h_done, (uint32_t)(16 * ks[j]));
+        did = true;
       }
-      ++kc;
-      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-      CBAR();
-      if (lane == 0) st_ctl(&L.c_ready, (uint32_t)kc);
-      did = true;
-    }
-    // Store out finished H chunks (the last chunk ends at 4G, which need not be a multiple of 16).
-    if (ks < B.NC && prog >= (16 * (ks + 1) < B.T_END ? 16 * (ks + 1) : B.T_END)) {
-      io_store_chunk<T>(B, L, ks);
-      ++ks;
-      __builtin_amdgcn_s_waitcnt(0xc07f);
-      CBAR();
-      if (lane == 0) st_ctl(&L.h_done, (uint32_t)(16 * ks));
-      did = true;
-    }
-    // Re-arm T slots the compute wave has validated (positions < progress + 64).
-    {
       int target = prog + 64;
-      if (target > B.T_END) target = B.T_END;
-      if (target > tr) {
-        const int nq = (target - tr) / 4;
+      if (target > B[j].T_END) target = B[j].T_END;
+      if (target > tr[j]) {
+        const int nq = (target - tr[j]) / 4;
         for (int base = 0; base < nq; base += 64) {
           if (base + lane < nq) {
-            const int p = tr + 4 * (base + lane);
+            const int p = tr[j] + 4 * (base + lane);
             u4 s4 = {SENT, SENT, SENT, SENT};
             lds_st4(L8(L.tring) + (p & (RING_T - 1)) * 4, s4);
           }
         }
-        tr = target;
+        tr[j] = target;
         __builtin_amdgcn_s_waitcnt(0xc07f);
         CBAR();
-        if (lane == 0) st_ctl(&L.t_reset, (uint32_t)tr);
+        if (lane == 0) st_ctl(&L.t_reset, (uint32_t)tr[j]);
         did = true;
       }
+      if (ks[j] < B[j].NC || tr[j] < B[j].T_END) done = false;
     }
-    // Wave 0 feeds its T ring from the top boundary or from the band above.
-    if (tw < B.T_END) {
-      int limit = tr + RING_T;
-      if (limit > B.T_END) limit = B.T_END;
-      if (tw < limit) {
-        const int got = io_feed_t<T, RULE>(B, L, tw, limit, hand_in);
-        if (got > 0) {
-          tw += got;
-          did = true;
+    if (rearm_hand) {
+      const int fed = (int)ld_ctl(&lds[0].t_fed);
+      if (fed > hr) {
+        const int nq = (fed - hr) / 4;
+        for (int base = 0; base < nq; base += 64) {
+          if (base + lane < nq) {
+            const int p = hr + 4 * (base + lane);
+            u4 s4 = {SENT, SENT, SENT, SENT};
+            __builtin_amdgcn_raw_buffer_store_b128(s4, hand_in, p * 4, 0, 0);
+          }
         }
+        hr = fed;
+        did = true;
       }
+      if (hr < hand_end) done = false;
     }
-    if (ks >= B.NC && tr >= B.T_END && tw >= B.T_END) break;
+    if (done) break;
     if (did) {
       t_idle = wall_clock64();
       continue;
     }
-    __builtin_amdgcn_s_sleep(1);
-    if (ld_ctl(&lds[0].abort)) return;
-    if ((++polls & 255u) == 0u && ld_dev(a.ctl + CTL_ABORT)) {
-      st_ctl(&lds[0].abort, 1u);
-      return;
+    if (!io_idle<false>(lds, a, t_idle, polls)) return;
+  }
+}
+
+// Feed the T ring of compute wave 0 (positions 60 .. T_END) from the top
+// boundary (band 0) or from the handoff row of the band above.
+template <typename T, int RULE, int W>
+__device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds* lds, int lane, const KArgs& a) {
+  const uint32_t SENT = Num<T>::SENT;
+  const BandGeom B = band_geom<W>(g, band, 0);
+  WaveLds& L = lds[0];
+  __amdgpu_buffer_rsrc_t hand_in =
+      make_rsrc(g.hand + (band > 0 ? (int64_t)(band - 1) * g.hand_ld : 0), (uint32_t)(g.hand_ld * 4));
+  int tw = 60;
+  uint64_t t_idle = wall_clock64();
+  uint32_t polls = 0;
+  while (tw < B.T_END) {
+    int limit = (int)ld_ctl(&L.t_reset) + RING_T;
+    if (limit > B.T_END) limit = B.T_END;
+    CBAR();
+    int got = 0;
+    if (tw < limit) {
+      const int nq = (limit - tw) / 4;
+      const int p = tw + 4 * lane;
+      const bool mine = lane < nq && lane < 16;
+      u4 v = {SENT, SENT, SENT, SENT};
+      bool valid = false;
+      if (mine) {
+        if (band == 0) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t ti = (int64_t)p + e - 62;  // index into top[] (= column + 1)
+            T val = Num<T>::template absent<RULE>();
+            if (ti >= 0 && ti <= B.n) {
+              if (g.top) val = ((const T*)g.top)[ti];
+              else if (ti == 0) val = (T)0;
+            }
+            v[e] = bits(val);
+          }
+          valid = true;
+        } else {
+          v = __builtin_amdgcn_raw_buffer_load_b128(hand_in, p * 4, 0, CPOL_SC1);
+          valid = v.x != SENT && v.y != SENT && v.z != SENT && v.w != SENT;
+        }
+      }
+      const uint64_t ok = __builtin_amdgcn_ballot_w64(valid);
+      const int nvalid = (int)__builtin_ctzll(~ok);  // leading run of valid quads
+      if (nvalid > 0) {
+        if (lane < nvalid) lds_st4(L8(L.tring) + (p & (RING_T - 1)) * 4, v);
+        tw += 4 * nvalid;
+        got = nvalid;
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        CBAR();
+        if (lane == 0) st_ctl(&L.t_fed, (uint32_t)tw);
+      }
     }
-    if (wall_clock64() - t_idle > a.watchdog_ticks) {
-      raise_abort(lds, a);
-      return;
+    if (got) {
+      t_idle = wall_clock64();
+      continue;
     }
+    if (!io_idle<true>(lds, a, t_idle, polls)) return;
   }
 }
 
 // ------------------------------------------------------------------ kernel
-// Two waves per SIMD (one compute, one IO) whatever W is, so at most 256 VGPRs.
+constexpr int storers_for(int W) { return (W + 1) / 2; }
+constexpr int waves_for(int W) { return 2 * W + storers_for(W) + 1; }
+
+// Three waves per SIMD at most, so at most 168 VGPRs each.
 template <typename T, int RULE, int W>
-__global__ __attribute__((amdgpu_flat_work_group_size(128 * W, 128 * W), amdgpu_waves_per_eu(2, 2)))
+__global__ __attribute__((amdgpu_flat_work_group_size(64 * waves_for(W), 64 * waves_for(W)),
+                          amdgpu_waves_per_eu(3, 3)))
 void wf_sweep_kernel(KArgs a) {
   __shared__ WaveLds lds[W];
   __shared__ uint32_t s_item;
@@ -601,11 +785,14 @@ void wf_sweep_kernel(KArgs a) {
         L.c_ready = 0;
         L.h_done = 0;
         // -16: nothing computed and no T quad validated yet.  The compute wave publishes 0
-        // only after it has validated the first quad (positions 60..63), so the IO wave
-        // cannot re-arm or refill that slot before it has been read.
+        // only after it has validated the first quad (positions 60..63), so the storer
+        // cannot re-arm, and the feeder cannot refill, that slot before it has been read.
         L.progress = (uint32_t)-16;
         L.t_reset = 60;
+        L.t_fed = 60;
         L.abort = 0;
+        L.tr_start = L.tr_first = L.tr_end = L.tr_wall = 0;
+        L.tr_chunk_wait = L.tr_t_wait = L.tr_load_wait = 0;
       }
     }
     __syncthreads();
@@ -622,8 +809,22 @@ void wf_sweep_kernel(KArgs a) {
       band = (int)t;
     }
     if (wave < W) compute_band<T, RULE, W>(gd, band, lds, wave, lane, a);
-    else io_band<T, RULE, W>(gd, band, lds, wave - W, lane, a);
+    else if (wave < 2 * W) loader_band<W>(gd, band, lds, wave - W, lane, a);
+    else if (wave < 2 * W + storers_for(W)) storer_band<T, W>(gd, band, lds, wave - 2 * W, lane, a);
+    else feeder_band<T, RULE, W>(gd, band, lds, lane, a);
     __syncthreads();
+    if (a.trace && wave < W && lane == 0) {
+      const WaveLds& L = lds[wave];
+      uint64_t* r = a.trace + ((uint64_t)t * W + wave) * TRACE_WORDS;
+      r[0] = ((uint64_t)(a.grids ? a.items[t].grid : 0) << 32) | ((uint64_t)band << 8) | (uint64_t)wave;
+      r[1] = L.tr_start;
+      r[2] = L.tr_first;
+      r[3] = L.tr_end;
+      r[4] = L.tr_chunk_wait;
+      r[5] = L.tr_t_wait;
+      r[6] = L.tr_load_wait;
+      r[7] = L.tr_wall;
+    }
   }
 }
 
@@ -634,7 +835,7 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
 
 template <typename T, int RULE, int W>
 hipError_t launch_t(int nwg, const KArgs& args, hipStream_t stream) {
-  hipLaunchKernelGGL((wf_sweep_kernel<T, RULE, W>), dim3(nwg), dim3(128 * W), 0, stream, args);
+  hipLaunchKernelGGL((wf_sweep_kernel<T, RULE, W>), dim3(nwg), dim3(64 * waves_for(W)), 0, stream, args);
   return hipGetLastError();
 }
 

@@ -202,7 +202,7 @@ static int choose_waves(int64_t m) {
   return 1;
 }
 
-static int wgs_per_cu(int W) { return W >= 4 ? 1 : (W == 2 ? 2 : 4); }
+static int wgs_per_cu(int W) { return W >= 4 ? 1 : (W == 2 ? 2 : 3); }
 
 static uint32_t sentinel_of(int dtype) { return dtype == WF_F32 ? SENT_F32 : SENT_I32; }
 
@@ -338,8 +338,30 @@ extern "C" wf_status wf_solve(wf_ctx* ctx, const wf_problem* p, void* stream_) {
   a.watchdog_ticks = ctx->watchdog_ticks;
   const int resident = ctx->num_cus * wgs_per_cu(W);
   const int nwg = (int)std::min<int64_t>(a.nitems, resident);
+  // Optional trace (profiling hook): WF_TRACE_FILE=<path> makes wf_solve synchronous
+  // and writes TRACE_WORDS uint64 per (band, compute wave) to <path>.
+  const char* trace_file = std::getenv("WF_TRACE_FILE");
+  uint64_t* trace = nullptr;
+  const size_t trace_words = (size_t)a.nitems * W * TRACE_WORDS;
+  if (trace_file && *trace_file) {
+    WF_HIP(hipMalloc(&trace, trace_words * sizeof(uint64_t)));
+    WF_HIP(hipMemsetAsync(trace, 0, trace_words * sizeof(uint64_t), stream));
+    a.trace = trace;
+  }
   WF_HIP(launch_fill_u32(s->ctl, 0u, CTL_WORDS, stream));
   WF_HIP(launch_sweep(p->dtype, p->rule, W, nwg, a, stream));
+  if (trace) {
+    std::vector<uint64_t> host(trace_words);
+    WF_HIP(hipMemcpyAsync(host.data(), trace, trace_words * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+    WF_HIP(hipStreamSynchronize(stream));
+    WF_HIP(hipFree(trace));
+    if (FILE* f = std::fopen(trace_file, "wb")) {
+      const uint64_t hdr[4] = {(uint64_t)a.nitems, (uint64_t)W, (uint64_t)TRACE_WORDS, (uint64_t)nwg};
+      std::fwrite(hdr, sizeof hdr, 1, f);
+      std::fwrite(host.data(), sizeof(uint64_t), host.size(), f);
+      std::fclose(f);
+    }
+  }
   return finish_launch(*s, stream);
 }
 
