@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X wavefront sweep.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batched] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batched] [--no-serving] [--no-cpu]
 
 One step = one sweep of the 16384 x 16384 fp32 grid (min rule, full output):
 one persistent kernel launch through the C ABI (wf_solve).  Inputs are
@@ -15,7 +15,10 @@ Prints ONE JSON line.  Besides the contract fields it carries
   cpu_baseline: the CPU oracle (fp64 row-major loop, one thread) on the same
                 workload;
   batched:      4096 grids, m and n log-uniform in [64, 2048], one persistent
-                launch (replayed hipGraph) against 4096 separate launches.
+                launch (replayed hipGraph) against 4096 separate launches;
+  serving:      Poisson arrivals of square grids (n log-uniform in [128, 8192])
+                at 0.7x the batched capacity of that mix, 64 GiB budget,
+                continuous batching: p50/p99 latency and cells/s.
 """
 from __future__ import annotations
 
@@ -42,6 +45,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-grids", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-load", type=float, default=0.7)
     return ap.parse_args()
 
 
@@ -127,6 +134,97 @@ def batched(torch, wf, wfgen, count):
             "shapes": "m, n independently log-uniform in [64, 2048] (PCG64 seed 4), grid g seed 1000+g"}
 
 
+def serving(torch, wf, wfgen, grids, requests, load):
+    """Poisson arrivals of square grids (n log-uniform in [128, 8192]) served under a
+    64 GiB budget with continuous batching.  The arrival rate is `load` times the
+    batched capacity for the same mix, measured first with one wf_solve_batched
+    launch.  Latency = completion observed by the server - submission."""
+    import numpy as np
+
+    reqs = wfgen.serving_requests(requests, rate_per_s=1.0)  # unit-rate arrival pattern, rescaled below
+    # `grids` distinct grids (the first draws of the recipe); request q serves grid q mod grids.
+    sizes = [n for (_, n, _) in reqs[:grids]]
+    costs = []
+    for g, n in enumerate(sizes):
+        t = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        wfgen.fill_device(t, seed=50000 + g)
+        costs.append(t)
+    torch.cuda.synchronize()
+    cells = [n * n for n in sizes]
+    # capacity of this mix when batched
+    outs = [torch.empty_like(c) for c in costs]
+    wf.solve_batched(costs, outs, use_graph=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wf.solve_batched(costs, outs, use_graph=0)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    wf.check()
+    del outs
+    cap = grids / t_batch
+    rate = load * cap
+    arrivals = [a / rate for (a, _, _) in reqs]
+    lat, cells_done = [], 0
+    with wf.Server(budget_bytes=64 << 30, max_inflight=4, max_batch=256) as srv:
+        # warm-up: one request of each distinct grid is not needed; a short burst warms the path
+        for g in range(min(8, grids)):
+            tk = srv.submit(costs[g])
+            while srv.poll_times(tk) is None:
+                time.sleep(1e-4)
+            srv.release(tk)
+        outstanding = {}
+        t_start = time.perf_counter()
+        i = 0
+        first_submit, last_done = None, 0.0
+        lag = []
+        while i < len(arrivals) or outstanding:
+            now = time.perf_counter()
+            while i < len(arrivals) and t_start + arrivals[i] <= now:
+                g = i % grids
+                tk = srv.submit(costs[g])
+                outstanding[tk] = (g, t_start + arrivals[i])
+                i += 1
+            progressed = False
+            for tk in list(outstanding)[:32]:
+                ts = srv.poll_times(tk)
+                if ts is None:
+                    continue
+                g, t_arr = outstanding.pop(tk)
+                srv.release(tk)
+                lat.append(ts[3] - ts[0])
+                lag.append(ts[0] - t_arr)
+                cells_done += cells[g]
+                first_submit = ts[0] if first_submit is None else min(first_submit, ts[0])
+                last_done = max(last_done, ts[3])
+                progressed = True
+            if not progressed and (i >= len(arrivals) or t_start + arrivals[i] > time.perf_counter() + 2e-4):
+                time.sleep(1e-4)
+        peak = srv.memory()[1]
+        # results served in the mix equal the same grids swept alone
+        checked = 0
+        for g in range(min(4, grids)):
+            tk = srv.submit(costs[g])
+            for h in range(4):  # a few companions so the check runs inside a batch
+                srv.submit(costs[(g + h + 1) % grids])
+            while (r := srv.poll(tk)) is None:
+                time.sleep(1e-4)
+            alone = wf.solve(costs[g])
+            torch.cuda.synchronize()
+            if not torch.equal(r["out"], alone):
+                raise AssertionError(f"served grid {g} differs from the grid swept alone")
+            checked += 1
+    wf.check()
+    lat = np.array(lat) * 1e3
+    span = last_done - first_submit
+    return {"requests": len(arrivals), "distinct_grids": grids,
+            "n": "log-uniform in [128, 8192] (PCG64 seed 5), grid g seed 50000+g, request q serves grid q mod %d" % grids,
+            "batched_capacity_req_per_s": cap, "load": load, "rate_req_per_s": rate,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "cells_per_s": cells_done / span,
+            "submit_lag_p99_ms": float(np.percentile(np.array(lag) * 1e3, 99)),
+            "peak_server_bytes": peak, "budget_bytes": 64 << 30, "checked_equal_alone": checked}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -195,6 +293,12 @@ def main():
             result["batched"] = batched(torch, wf, wfgen, args.batch_count)
         except Exception as e:  # report, do not lose the main line
             result["batched"] = {"error": repr(e)}
+    if not args.no_serving:
+        log(f"[bench] serving: {args.serve_requests} requests over {args.serve_grids} grids")
+        try:
+            result["serving"] = serving(torch, wf, wfgen, args.serve_grids, args.serve_requests, args.serve_load)
+        except Exception as e:  # report, do not lose the main line
+            result["serving"] = {"error": repr(e)}
     if not args.no_cpu:
         log(f"[bench] cpu baseline ({args.cpu_seconds:.0f} s of one core)")
         result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -105,7 +105,8 @@ typedef struct wf_tuning {
   int32_t waves_per_wg;    /* compute waves per workgroup: 1, 2 or 4 (0 = automatic) */
   int32_t max_wgs;         /* persistent workgroups per launch (0 = automatic) */
   int32_t order;           /* batched work order: 0 = automatic, 1 = grid-major, 2 = interleaved by band */
-  int32_t use_graph;       /* batched: 1 = capture and replay a hipGraph (default), 0 = plain launch, -1 = automatic */
+  int32_t use_graph;       /* batched: 1 = capture and replay a hipGraph, 0 = plain launch,
+                              -1 = plain launch without autotuning */
   int32_t reserved[4];     /* must be 0 */
 } wf_tuning;
 
@@ -123,9 +124,15 @@ wf_status wf_solve(wf_ctx* ctx, const wf_problem* p, void* stream);
 /* Sweep `count` independent grids of any sizes in one persistent launch on
  * `stream`; the bands of all grids are packed into one work list so the thin
  * first and last diagonals of one grid overlap the wide middle of another.
- * `t` may be NULL (tuned defaults from the context's tuning table).  The
- * launch is captured in a hipGraph and replayed when the same batch shape
- * (count, sizes, dtype/rule/mode) is solved again. */
+ * All grids of one call share dtype and rule (WF_EUNSUPPORTED otherwise).
+ * Autotuning: when `t` is NULL or leaves both waves_per_wg and order at 0 (and
+ * use_graph is not -1), the first call for a batch shape (count, sizes, dtype,
+ * rule, mode) runs the batch once per candidate configuration (waves per
+ * workgroup 1, 2, 4 x grid-major / interleaved order), synchronously, timed
+ * on `stream`, and keeps the fastest in the context's tuning table; later
+ * calls with that shape use it.  Every trial writes the full, correct result.
+ * With use_graph = 1 the chosen launch is captured in a hipGraph and replayed
+ * when the same batch shape is solved again. */
 wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t count, const wf_tuning* t, void* stream);
 
 /* Wait for all work this context has enqueued and return WF_ETIMEDOUT if the

@@ -234,3 +234,119 @@ def solve_batched(costs, outs=None, rule: str = "min", mode: str = "full", strea
 def check(device: int | None = None):
     """Wait for the context's work; raise WfError if a device watchdog fired."""
     _check(load_library().wf_check(context(device)))
+
+
+class _DeviceArray:
+    """A zero-copy view of server-owned device memory for torch.as_tensor."""
+
+    def __init__(self, ptr: int, shape, typestr: str, strides=None):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (ptr, False),
+                                         "version": 2, "strides": strides}
+
+
+class Server:
+    """Serving front end (wf_server_* in the C ABI).
+
+    Requests are admitted against a device-memory budget as they arrive and
+    batched into persistent launches on up to `max_inflight` streams while
+    earlier launches still run.  Results stay in server memory until released.
+
+        srv = Server(budget_bytes=8 << 30)
+        t = srv.submit(cost)                  # device tensor (kept alive until done) or host array
+        r = srv.poll(t)                       # None while pending
+        H = r["out"]                          # torch view of server memory; copy before release
+        srv.release(t)
+    """
+
+    def __init__(self, budget_bytes: int = 0, max_inflight: int = 0, max_batch: int = 0, device: int | None = None):
+        lib = load_library()
+        o = ServerOpts()
+        o.hbm_budget_bytes, o.max_inflight, o.max_batch = budget_bytes, max_inflight, max_batch
+        self._h = _P()
+        _check(lib.wf_server_create(context(device), ctypes.byref(o), ctypes.byref(self._h)))
+        self._keep = {}
+
+    def submit(self, cost, rule: str = "min", mode: str = "full") -> int:
+        """Queue one grid; `cost` is a 2-D float32/int32 device tensor or a C-contiguous host
+        numpy array.  Returns the ticket."""
+        import numpy as np
+        r = Request()
+        if hasattr(cost, "is_cuda") and cost.is_cuda:
+            m, n = cost.shape
+            r.dtype = DTYPES[_dtype_of(cost)]
+            r.input_kind, r.input, r.ld_input = 0, cost.data_ptr(), _ld(cost, n)
+        else:
+            a = np.ascontiguousarray(cost)
+            if a.dtype == np.float32:
+                r.dtype = 0
+            elif a.dtype == np.int32:
+                r.dtype = 1
+            else:
+                raise TypeError("cost must be float32 or int32")
+            m, n = a.shape
+            cost = a
+            r.input_kind, r.input, r.ld_input = 1, a.ctypes.data, n
+        r.m, r.n, r.rule, r.mode = m, n, RULES[rule], MODES[mode]
+        t = ctypes.c_uint64()
+        _check(load_library().wf_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = (cost, m, n, r.dtype, mode)
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending; else a dict with torch views of the results and timestamps."""
+        import torch
+        res = Result()
+        st = load_library().wf_poll(self._h, ticket, ctypes.byref(res))
+        if st == WF_PENDING:
+            return None
+        _check(st)
+        _, m, n, dt, mode = self._keep[ticket]
+        ts = "<f4" if dt == 0 else "<i4"
+
+        def view(ptr, shape, strides=None):
+            if not ptr or 0 in shape:
+                return None
+            return torch.as_tensor(_DeviceArray(ptr, shape, ts, strides), device="cuda")
+
+        return {"out": view(res.out, (m, n), (res.ld_out * 4, 4)) if mode == "full" else None,
+                "last_row": view(res.last_row, (n,)), "last_col": view(res.last_col, (m,)),
+                "final_cell": view(res.final_cell, (1,)),
+                "t_submit": res.t_submit, "t_admit": res.t_admit, "t_launch": res.t_launch, "t_done": res.t_done}
+
+    def poll_times(self, ticket: int):
+        """None while pending; else (t_submit, t_admit, t_launch, t_done) on the server's
+        monotonic clock (the clock of time.perf_counter on Linux)."""
+        res = Result()
+        st = load_library().wf_poll(self._h, ticket, ctypes.byref(res))
+        if st == WF_PENDING:
+            return None
+        _check(st)
+        return res.t_submit, res.t_admit, res.t_launch, res.t_done
+
+    def release(self, ticket: int):
+        _check(load_library().wf_release(self._h, ticket))
+        self._keep.pop(ticket, None)
+
+    def memory(self):
+        """(bytes held for requests now, peak)."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(load_library().wf_server_memory(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def close(self):
+        if self._h:
+            _check(load_library().wf_server_destroy(self._h))
+            self._h = _P()
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -35,6 +35,8 @@ struct KArgs {
   uint32_t* ctl;          // [0] ticket counter, [1] error code, [2] abort flag
   uint64_t watchdog_ticks;
   uint64_t* trace;        // optional: TRACE_WORDS per (work item, compute wave), see below
+  uint64_t* ctrace;       // optional: CTRACE_WORDS per (work item, compute wave, chunk), see below
+  int64_t ctrace_nc;      // chunks per (work item, compute wave) in ctrace
 };
 
 // Per (work item, compute wave) trace record, written when KArgs::trace is set:
@@ -44,6 +46,12 @@ struct KArgs {
 //   [5] cycles waiting for top-boundary quads   [6] loader cycles waiting for a free c slot
 //   [7] wall clock (100 MHz) at band start
 constexpr int TRACE_WORDS = 8;
+// Per-chunk trace record (compute waves, when KArgs::ctrace is set):
+//   [0] wall clock on reaching the chunk start   [1] wall clock when its wait ended
+//   [2] cycles spent so far waiting for top-boundary quads (needs KArgs::trace)
+//   [3] which conditions were not met on arrival: 1 c ring, 2 H ring, 4 own T ring,
+//       8 consumer's T ring
+constexpr int CTRACE_WORDS = 4;
 
 // Control-word indices.
 enum { CTL_TICKET = 0, CTL_ERROR = 1, CTL_ABORT = 2, CTL_WORDS = 4 };

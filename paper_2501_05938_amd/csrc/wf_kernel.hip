@@ -147,6 +147,13 @@ constexpr int CPOL_SC1 = 16;  // device-scope coherent access
 
 typedef __attribute__((address_space(1))) uint32_t glb_u32;
 __device__ __forceinline__ glb_u32* G32(uint32_t* p) { return (glb_u32*)(void*)p; }
+// Global-address-space views of plain pointers.  Generic (flat) accesses would also
+// count on the LDS counter, so every wait for an LDS access would wait for them too.
+typedef __attribute__((address_space(1))) u4a4 glb_u4a4;
+__device__ __forceinline__ glb_u4a4* G128(uint32_t* p) { return (glb_u4a4*)(void*)p; }
+template <typename T> __device__ __forceinline__ const __attribute__((address_space(1))) T* GC(const void* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
 __device__ __forceinline__ uint32_t ld_dev(uint32_t* p) {
   return __hip_atomic_load(G32(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -231,9 +238,12 @@ template <typename T, int RULE, int KIND, int CONS>
 __device__ __forceinline__ void compute_chunk(
     int k, int G, int gT, int NCc, WaveLds* lds, WaveLds& L, WaveLds* C,
     __amdgpu_buffer_rsrc_t hand_out, lds_u8* crow, lds_u8* hrow, lds_u8* ct_base, bool lane63, int lane,
-    u4 (&cq)[4], u4 (&tq)[4], uint32_t& tprev_w, T& H, T& Np, const KArgs& a) {
+    u4 (&cq)[4], u4 (&tq)[4], uint32_t& tprev_w, T& H, T& Np, const KArgs& a, uint64_t* crec) {
   const uint32_t SENT = Num<T>::SENT;
   const int pos = CHUNK * k;
+  __attribute__((address_space(1))) uint64_t* rec =
+      crec ? (__attribute__((address_space(1))) uint64_t*)(void*)(crec + (int64_t)k * CTRACE_WORDS) : nullptr;
+  if (rec && lane == 0) rec[0] = wall_clock64();
   // Chunk start: publish progress, then wait until the c ring holds this chunk and the next
   // (reads run two groups ahead), the H slots are free, and the consumer's T slots are re-armed.
   CBAR();
@@ -254,8 +264,17 @@ __device__ __forceinline__ void compute_chunk(
     };
     if (!ready()) {
       const uint64_t c0 = __builtin_readcyclecounter();
+      if (rec && lane == 0) {
+        rec[3] = ((int)ld_ctl(&L.c_ready) < need_c ? 1u : 0u) | ((int)ld_ctl(&L.h_done) < need_h ? 2u : 0u) |
+                 ((int)ld_ctl(&L.t_reset) < need_own_t ? 4u : 0u) |
+                 (CONS == 1 && (int)ld_ctl(&C->t_reset) < need_t ? 8u : 0u);
+      }
       wait_until<false>(ready, lds, a);
       if (a.trace && lane == 0) L.tr_chunk_wait += __builtin_readcyclecounter() - c0;
+    }
+    if (rec && lane == 0) {
+      rec[1] = wall_clock64();
+      rec[2] = L.tr_t_wait;
     }
   }
   CBAR();
@@ -329,7 +348,7 @@ __device__ __forceinline__ void compute_chunk(
 
 template <typename T, int RULE, int CONS>
 __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLds& L, WaveLds* C, __amdgpu_buffer_rsrc_t hand_out,
-                             lds_u8* crow, lds_u8* hrow, int lane, T H, const KArgs& a) {
+                             lds_u8* crow, lds_u8* hrow, int lane, T H, const KArgs& a, uint64_t* crec) {
   const int NCc = (4 * G + CHUNK - 1) / CHUNK;
   lds_u8* ct_base = CONS == 1 ? L8(C->tring) : nullptr;
   const bool lane63 = lane == 63;
@@ -353,19 +372,20 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   int k = 0;
   for (; k < 4; ++k)
     compute_chunk<T, RULE, 0, CONS>(k, G, gT, NCc, lds, L, C, hand_out, crow, hrow, ct_base, lane63, lane,
-                                    cq, tq, tprev_w, H, Np, a);
+                                    cq, tq, tprev_w, H, Np, a, crec);
   for (; 4 * k + 6 <= gT; ++k)
     compute_chunk<T, RULE, 1, CONS>(k, G, gT, NCc, lds, L, C, hand_out, crow, hrow, ct_base, lane63, lane,
-                                    cq, tq, tprev_w, H, Np, a);
+                                    cq, tq, tprev_w, H, Np, a, crec);
   for (; k < NCc; ++k)
     compute_chunk<T, RULE, 2, CONS>(k, G, gT, NCc, lds, L, C, hand_out, crow, hrow, ct_base, lane63, lane,
-                                    cq, tq, tprev_w, H, Np, a);
+                                    cq, tq, tprev_w, H, Np, a, crec);
   CBAR();
   if (lane == 0) st_ctl(&L.progress, (uint32_t)(4 * G));
 }
 
 template <typename T, int RULE, int W>
-__device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLds* lds, int w, int lane, const KArgs& a) {
+__device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLds* lds, int w, int lane, const KArgs& a,
+                                             uint64_t* crec) {
   WaveLds& L = lds[w];
   const int64_t m = g.m, n = g.n;
   const int64_t row0 = (int64_t)band * (64 * W) + 64 * w;
@@ -380,16 +400,16 @@ __device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLd
     L.tr_wall = wall_clock64();
   }
   T H = Num<T>::template absent<RULE>();
-  if (g.left && row < m) H = ((const T*)g.left)[row];
+  if (g.left && row < m) H = GC<T>(g.left)[row];
   lds_u8* crow = L8(L.cring) + lane_off(lane);
   lds_u8* hrow = L8(L.hring) + lane_off(lane);
   if (lds_consumer) {
-    compute_walk<T, RULE, 1>(G, gT, lds, L, &lds[w + 1], __amdgpu_buffer_rsrc_t(), crow, hrow, lane, H, a);
+    compute_walk<T, RULE, 1>(G, gT, lds, L, &lds[w + 1], __amdgpu_buffer_rsrc_t(), crow, hrow, lane, H, a, crec);
   } else if (glob_consumer) {
     __amdgpu_buffer_rsrc_t hand_out = make_rsrc(g.hand + (int64_t)band * g.hand_ld, (uint32_t)(g.hand_ld * 4));
-    compute_walk<T, RULE, 2>(G, gT, lds, L, nullptr, hand_out, crow, hrow, lane, H, a);
+    compute_walk<T, RULE, 2>(G, gT, lds, L, nullptr, hand_out, crow, hrow, lane, H, a, crec);
   } else {
-    compute_walk<T, RULE, 0>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), crow, hrow, lane, H, a);
+    compute_walk<T, RULE, 0>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), crow, hrow, lane, H, a, crec);
   }
   if (a.trace && lane == 0) L.tr_end = __builtin_readcyclecounter();
 }
@@ -589,9 +609,9 @@ __device__ __forceinline__ void store_chunk(const GridDesc& g, const BandGeom& B
     const int64_t col = 16 * k + 4 * (lane >> 4) - rho;
     if (row >= B.m || col > B.n - 1 || col + 3 < 0) continue;
     if (full) {
-      uint32_t* op = (uint32_t*)g.out + row * g.ld_out;
+      glb_u32* op = G32((uint32_t*)g.out + row * g.ld_out);
       if (col >= 0 && col + 3 <= B.n - 1) {
-        *(u4a4*)(op + col) = v[i];
+        *(glb_u4a4*)(op + col) = v[i];
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
@@ -599,14 +619,14 @@ __device__ __forceinline__ void store_chunk(const GridDesc& g, const BandGeom& B
       }
     }
     const bool has_last = col <= B.n - 1 && col + 3 >= B.n - 1;
-    if (has_last && g.last_col) ((uint32_t*)g.last_col)[row] = pick(v[i], (int)(B.n - 1 - col));
+    if (has_last && g.last_col) G32((uint32_t*)g.last_col)[row] = pick(v[i], (int)(B.n - 1 - col));
     if (row == B.m - 1) {
       if (g.last_row) {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          if (col + e >= 0 && col + e <= B.n - 1) ((uint32_t*)g.last_row)[col + e] = pick(v[i], e);
+          if (col + e >= 0 && col + e <= B.n - 1) G32((uint32_t*)g.last_row)[col + e] = pick(v[i], e);
       }
-      if (has_last && g.final_cell) *(uint32_t*)g.final_cell = pick(v[i], (int)(B.n - 1 - col));
+      if (has_last && g.final_cell) *G32((uint32_t*)g.final_cell) = pick(v[i], (int)(B.n - 1 - col));
     }
   }
 }
@@ -727,7 +747,7 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
             const int64_t ti = (int64_t)p + e - 62;  // index into top[] (= column + 1)
             T val = Num<T>::template absent<RULE>();
             if (ti >= 0 && ti <= B.n) {
-              if (g.top) val = ((const T*)g.top)[ti];
+              if (g.top) val = GC<T>(g.top)[ti];
               else if (ti == 0) val = (T)0;
             }
             v[e] = bits(val);
@@ -808,7 +828,10 @@ void wf_sweep_kernel(KArgs a) {
       gd = a.g0;
       band = (int)t;
     }
-    if (wave < W) compute_band<T, RULE, W>(gd, band, lds, wave, lane, a);
+    if (wave < W) {
+      uint64_t* crec = a.ctrace ? a.ctrace + ((int64_t)t * W + wave) * a.ctrace_nc * CTRACE_WORDS : nullptr;
+      compute_band<T, RULE, W>(gd, band, lds, wave, lane, a, crec);
+    }
     else if (wave < 2 * W) loader_band<W>(gd, band, lds, wave - W, lane, a);
     else if (wave < 2 * W + storers_for(W)) storer_band<T, W>(gd, band, lds, wave - 2 * W, lane, a);
     else feeder_band<T, RULE, W>(gd, band, lds, lane, a);

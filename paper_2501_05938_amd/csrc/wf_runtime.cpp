@@ -3,6 +3,7 @@
 // replay, and error reporting.
 #include "../../include/wf.h"
 #include "wf_internal.h"
+#include "wf_host.h"
 
 #include <algorithm>
 #include <atomic>
@@ -17,21 +18,15 @@
 #include <vector>
 
 using namespace wfk;
+using namespace wfh;
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_last_error;
 
-static wf_status fail(wf_status s, const std::string& msg) {
+wf_status wfh::fail(wf_status s, const std::string& msg) {
   g_last_error = msg;
   return s;
 }
-
-#define WF_HIP(call)                                                                     \
-  do {                                                                                   \
-    hipError_t e_ = (call);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return fail(WF_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));           \
-  } while (0)
 
 extern "C" const char* wf_last_error(void) { return g_last_error.c_str(); }
 
@@ -53,42 +48,7 @@ extern "C" const char* wf_status_str(wf_status s) {
 
 extern "C" const char* wf_version(void) { return "libwf 0.1 (gfx950)"; }
 
-// --------------------------------------------------------------- workspace
-// A launch slot owns everything one in-flight launch mutates: control words,
-// handoff rows, descriptor table and work list.  Slots are reused round-robin
-// once their last launch has completed.
-struct Slot {
-  uint32_t* ctl = nullptr;        // CTL_WORDS device words
-  uint32_t* hand = nullptr;       // handoff rows (kept at the sentinel between launches)
-  size_t hand_cap = 0;            // in uint32 elements
-  uint32_t hand_sent = 0;         // sentinel the handoff rows currently hold
-  GridDesc* grids = nullptr;      // batched descriptor table
-  size_t grids_cap = 0;
-  Item* items = nullptr;          // batched work list
-  size_t items_cap = 0;
-  uint32_t* host_err = nullptr;   // pinned copy of ctl[CTL_ERROR] after the launch
-  hipEvent_t done = nullptr;      // recorded after the launch and the error copy
-  bool pending = false;           // a launch was recorded and not yet checked
-};
-
-struct GraphEntry {
-  hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
-  int slot = -1;
-};
-
-struct wf_ctx {
-  int device = 0;
-  int num_cus = 256;
-  uint64_t watchdog_ticks = 200000000ull;  // 2 s of the 100 MHz device wall clock
-  static constexpr int NSLOT = 8;
-  Slot slots[NSLOT];
-  int next_slot = 0;
-  std::map<std::string, GraphEntry> graphs;
-  wf_status sticky = WF_OK;                // device error seen, reported once
-};
-
-static wf_status set_device(wf_ctx* ctx) {
+wf_status wfh::set_device(wf_ctx* ctx) {
   int cur = -1;
   WF_HIP(hipGetDevice(&cur));
   if (cur != ctx->device) WF_HIP(hipSetDevice(ctx->device));
@@ -171,7 +131,7 @@ static wf_status ensure_buf(T** p, size_t* cap, size_t need) {
 // --------------------------------------------------------------- checking
 static const int64_t MAX_N = (int64_t)1 << 28;  // positions are 32-bit inside the kernel
 
-static wf_status check_problem(const wf_problem* p, int64_t idx) {
+wf_status wfh::check_problem(const wf_problem* p, int64_t idx) {
   char where[64] = "";
   if (idx >= 0) snprintf(where, sizeof where, "problem %lld: ", (long long)idx);
   if (!p) return fail(WF_EINVAL, std::string(where) + "NULL problem");
@@ -194,7 +154,7 @@ static wf_status check_problem(const wf_problem* p, int64_t idx) {
 }
 
 // ------------------------------------------------------------ configuration
-static int choose_waves(int64_t m) {
+int wfh::choose_waves(int64_t m) {
   // Bands of 64*W rows.  Inside a workgroup the bottom-row handoff goes through
   // LDS; across workgroups it goes through memory, so tall grids want W = 4.
   if (m >= 2048) return 4;
@@ -202,11 +162,11 @@ static int choose_waves(int64_t m) {
   return 1;
 }
 
-static int wgs_per_cu(int W) { return W >= 4 ? 1 : (W == 2 ? 2 : 3); }
+int wfh::wgs_per_cu(int W) { return W >= 4 ? 1 : (W == 2 ? 2 : 3); }
 
-static uint32_t sentinel_of(int dtype) { return dtype == WF_F32 ? SENT_F32 : SENT_I32; }
+uint32_t wfh::sentinel_of(int dtype) { return dtype == WF_F32 ? SENT_F32 : SENT_I32; }
 
-static GridDesc make_desc(const wf_problem* p, int W, uint32_t* hand) {
+GridDesc wfh::make_desc(const wf_problem* p, int W, uint32_t* hand) {
   GridDesc d;
   d.cost = p->cost;
   d.out = p->mode == WF_MODE_FULL ? p->out : nullptr;
@@ -226,7 +186,7 @@ static GridDesc make_desc(const wf_problem* p, int W, uint32_t* hand) {
   return d;
 }
 
-static size_t hand_elems(const wf_problem* p, int W) {
+size_t wfh::hand_elems(const wf_problem* p, int W) {
   const int64_t nb = (p->m + 64 * W - 1) / (64 * W);
   return nb > 1 ? (size_t)(nb - 1) * (size_t)hand_ld_for(p->n) : 0;
 }
@@ -343,22 +303,38 @@ extern "C" wf_status wf_solve(wf_ctx* ctx, const wf_problem* p, void* stream_) {
   const char* trace_file = std::getenv("WF_TRACE_FILE");
   uint64_t* trace = nullptr;
   const size_t trace_words = (size_t)a.nitems * W * TRACE_WORDS;
+  // With WF_TRACE_CHUNKS=1 it also writes CTRACE_WORDS uint64 per (band, compute wave, chunk).
+  const int64_t nc = (4 * groups_for(p->n) + 15) / 16;
+  const bool chunks = trace_file && *trace_file && std::getenv("WF_TRACE_CHUNKS");
+  const size_t ctrace_words = chunks ? (size_t)a.nitems * W * (size_t)nc * CTRACE_WORDS : 0;
+  uint64_t* ctrace = nullptr;
   if (trace_file && *trace_file) {
     WF_HIP(hipMalloc(&trace, trace_words * sizeof(uint64_t)));
-    WF_HIP(hipMemsetAsync(trace, 0, trace_words * sizeof(uint64_t), stream));
+    WF_HIP(launch_fill_u32((uint32_t*)trace, 0u, (int64_t)trace_words * 2, stream));
     a.trace = trace;
+    if (chunks) {
+      WF_HIP(hipMalloc(&ctrace, ctrace_words * sizeof(uint64_t)));
+      WF_HIP(launch_fill_u32((uint32_t*)ctrace, 0u, (int64_t)ctrace_words * 2, stream));
+      a.ctrace = ctrace;
+      a.ctrace_nc = nc;
+    }
   }
   WF_HIP(launch_fill_u32(s->ctl, 0u, CTL_WORDS, stream));
   WF_HIP(launch_sweep(p->dtype, p->rule, W, nwg, a, stream));
   if (trace) {
-    std::vector<uint64_t> host(trace_words);
+    std::vector<uint64_t> host(trace_words), chost(ctrace_words);
     WF_HIP(hipMemcpyAsync(host.data(), trace, trace_words * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+    if (ctrace)
+      WF_HIP(hipMemcpyAsync(chost.data(), ctrace, ctrace_words * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
     WF_HIP(hipStreamSynchronize(stream));
     WF_HIP(hipFree(trace));
+    if (ctrace) WF_HIP(hipFree(ctrace));
     if (FILE* f = std::fopen(trace_file, "wb")) {
-      const uint64_t hdr[4] = {(uint64_t)a.nitems, (uint64_t)W, (uint64_t)TRACE_WORDS, (uint64_t)nwg};
+      const uint64_t hdr[6] = {(uint64_t)a.nitems, (uint64_t)W, (uint64_t)TRACE_WORDS, (uint64_t)nwg,
+                               (uint64_t)(ctrace ? nc : 0), (uint64_t)CTRACE_WORDS};
       std::fwrite(hdr, sizeof hdr, 1, f);
       std::fwrite(host.data(), sizeof(uint64_t), host.size(), f);
+      if (ctrace) std::fwrite(chost.data(), sizeof(uint64_t), chost.size(), f);
       std::fclose(f);
     }
   }
@@ -379,39 +355,10 @@ static std::string batch_key(const wf_problem* ps, int64_t count, int W, int nwg
   return k;
 }
 
-extern "C" wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t count, const wf_tuning* t,
-                                      void* stream_) {
-  if (!ctx) return fail(WF_EINVAL, "ctx is NULL");
-  if (count < 0 || (count > 0 && !ps)) return fail(WF_EINVAL, "bad problem array");
-  if (count == 0) return WF_OK;
-  for (int64_t i = 0; i < count; ++i) {
-    wf_status st = check_problem(&ps[i], i);
-    if (st != WF_OK) return st;
-    if (ps[i].dtype != ps[0].dtype || ps[i].rule != ps[0].rule)
-      return fail(WF_EUNSUPPORTED, "all problems of a batch must share dtype and rule");
-  }
-  wf_tuning tun;
-  std::memset(&tun, 0, sizeof tun);
-  if (t) tun = *t;
-  for (int i = 0; i < 4; ++i)
-    if (tun.reserved[i] != 0) return fail(WF_EINVAL, "wf_tuning.reserved must be 0");
-  if (tun.waves_per_wg != 0 && tun.waves_per_wg != 1 && tun.waves_per_wg != 2 && tun.waves_per_wg != 4)
-    return fail(WF_EINVAL, "waves_per_wg must be 0, 1, 2 or 4");
-  if (tun.max_wgs < 0 || tun.order < 0 || tun.order > 2 || tun.use_graph < -1 || tun.use_graph > 1)
-    return fail(WF_EINVAL, "bad tuning value");
-  wf_status st = set_device(ctx);
-  if (st != WF_OK) return st;
-  st = report_sticky(ctx);
-  if (st != WF_OK) return st;
-  hipStream_t stream = (hipStream_t)stream_;
-
-  // Configuration.
-  int64_t max_m = 0;
-  for (int64_t i = 0; i < count; ++i) max_m = std::max(max_m, ps[i].m);
-  const int W = tun.waves_per_wg ? tun.waves_per_wg : choose_waves(max_m / 2 > 0 ? max_m / 2 : 1);
-  const int order = tun.order ? tun.order : 1;
-  const bool use_graph = tun.use_graph != 0;
-
+// One batched launch at a fixed configuration (arguments already checked).
+static wf_status batched_run(wf_ctx* ctx, const wf_problem* ps, int64_t count, int W, int order, int max_wgs,
+                             bool use_graph, hipStream_t stream) {
+  wf_status st = WF_OK;
   // Grids in work order: largest first so the long critical paths start early.
   std::vector<int64_t> perm;
   perm.reserve((size_t)count);
@@ -445,7 +392,7 @@ extern "C" wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t
   }
   const int resident = ctx->num_cus * wgs_per_cu(W);
   int nwg = (int)std::min<int64_t>((int64_t)items.size(), resident);
-  if (tun.max_wgs > 0) nwg = std::min(nwg, tun.max_wgs);
+  if (max_wgs > 0) nwg = std::min(nwg, max_wgs);
 
   const std::string key = use_graph ? batch_key(ps, count, W, nwg, order) : std::string();
   Slot* s = nullptr;
@@ -523,4 +470,99 @@ extern "C" wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t
     WF_HIP(launch_sweep(ps[0].dtype, ps[0].rule, W, nwg, a, stream));
   }
   return finish_launch(*s, stream);
+}
+
+// Autotuning: the first batch of a given shape signature (and no explicit
+// waves_per_wg / order) is run once at every candidate configuration, timed
+// with events on the caller's stream, and the fastest is kept for that
+// signature.  Every trial computes the full, correct result.
+static std::string shape_signature(const wf_problem* ps, int64_t count) {
+  return batch_key(ps, count, 0, 0, 0);
+}
+
+static wf_status autotune(wf_ctx* ctx, const wf_problem* ps, int64_t count, int max_wgs, hipStream_t stream,
+                          int* W_out, int* order_out) {
+  const std::string sig = shape_signature(ps, count);
+  auto it = ctx->tuned.find(sig);
+  if (it != ctx->tuned.end()) {
+    *W_out = it->second.first;
+    *order_out = it->second.second;
+    return WF_OK;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  WF_HIP(hipEventCreate(&e0));
+  WF_HIP(hipEventCreate(&e1));
+  float best = -1.f;
+  int bw = 1, bo = 1;
+  static const int Ws[] = {1, 2, 4};
+  wf_status st = WF_OK;
+  for (int W : Ws) {
+    for (int order = 1; order <= 2 && st == WF_OK; ++order) {
+      hipError_t e = hipEventRecord(e0, stream);
+      if (e == hipSuccess) st = batched_run(ctx, ps, count, W, order, max_wgs, false, stream);
+      if (st == WF_OK && e == hipSuccess) e = hipEventRecord(e1, stream);
+      if (st == WF_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (st == WF_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (st == WF_OK && e != hipSuccess) st = fail(WF_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+      if (st != WF_OK) break;
+      st = report_sticky(ctx);
+      if (st != WF_OK) break;
+      if (best < 0.f || ms < best) {
+        best = ms;
+        bw = W;
+        bo = order;
+      }
+    }
+    if (st != WF_OK) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != WF_OK) return st;
+  ctx->tuned[sig] = std::make_pair(bw, bo);
+  *W_out = bw;
+  *order_out = bo;
+  return WF_OK;
+}
+
+extern "C" wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t count, const wf_tuning* t,
+                                      void* stream_) {
+  if (!ctx) return fail(WF_EINVAL, "ctx is NULL");
+  if (count < 0 || (count > 0 && !ps)) return fail(WF_EINVAL, "bad problem array");
+  if (count == 0) return WF_OK;
+  for (int64_t i = 0; i < count; ++i) {
+    wf_status st = check_problem(&ps[i], i);
+    if (st != WF_OK) return st;
+    if (ps[i].dtype != ps[0].dtype || ps[i].rule != ps[0].rule)
+      return fail(WF_EUNSUPPORTED, "all problems of a batch must share dtype and rule");
+  }
+  wf_tuning tun;
+  std::memset(&tun, 0, sizeof tun);
+  if (t) tun = *t;
+  for (int i = 0; i < 4; ++i)
+    if (tun.reserved[i] != 0) return fail(WF_EINVAL, "wf_tuning.reserved must be 0");
+  if (tun.waves_per_wg != 0 && tun.waves_per_wg != 1 && tun.waves_per_wg != 2 && tun.waves_per_wg != 4)
+    return fail(WF_EINVAL, "waves_per_wg must be 0, 1, 2 or 4");
+  if (tun.max_wgs < 0 || tun.order < 0 || tun.order > 2 || tun.use_graph < -1 || tun.use_graph > 1)
+    return fail(WF_EINVAL, "bad tuning value");
+  wf_status st = set_device(ctx);
+  if (st != WF_OK) return st;
+  st = report_sticky(ctx);
+  if (st != WF_OK) return st;
+  hipStream_t stream = (hipStream_t)stream_;
+  bool any = false;
+  for (int64_t i = 0; i < count && !any; ++i) any = ps[i].m > 0 && ps[i].n > 0;
+  if (!any) return WF_OK;
+  int W = tun.waves_per_wg, order = tun.order;
+  if (W == 0 && order == 0 && tun.use_graph != -1) {
+    st = autotune(ctx, ps, count, tun.max_wgs, stream, &W, &order);
+    if (st != WF_OK) return st;
+  }
+  if (W == 0) {
+    int64_t max_m = 0;
+    for (int64_t i = 0; i < count; ++i) max_m = std::max(max_m, ps[i].m);
+    W = choose_waves(max_m / 2 > 0 ? max_m / 2 : 1);
+  }
+  if (order == 0) order = 1;
+  return batched_run(ctx, ps, count, W, order, tun.max_wgs, tun.use_graph == 1, stream);
 }

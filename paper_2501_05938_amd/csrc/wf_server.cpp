@@ -1,11 +1,563 @@
-// wf_server.cpp -- serving front end (admission by HBM budget, continuous batching).
+// wf_server.cpp -- serving front end: requests are admitted against a device
+// memory budget as they arrive, batched into persistent sweep launches on
+// several streams while earlier launches are still running (continuous
+// batching), and completed asynchronously.
+//
+// One server thread owns every HIP call of the server.  Per pass it
+//   1. retires launches whose completion event has fired (results stay in
+//      server memory until wf_release),
+//   2. admits queued requests in arrival order while their memory fits the
+//      budget (a first-fit arena carved from one device allocation),
+//   3. packs the admitted requests that share dtype and rule into one launch
+//      on a free stream: host inputs are copied in, handoff rows are armed,
+//      the descriptor table and work list are uploaded from pinned staging,
+//      and the persistent kernel runs their bands in ticket order.
+// Launches on different streams overlap on the device: a launch's workgroups
+// retire as its ticket list runs out, and the next launch's workgroups take
+// their place.  Each launch has its own ticket counter, and a band only waits
+// on a band of the same launch with a smaller ticket, so concurrent launches
+// cannot deadlock one another.
 #include "../../include/wf.h"
+#include "wf_host.h"
+#include "wf_internal.h"
 
-struct wf_server {};
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
 
-extern "C" wf_status wf_server_create(wf_ctx*, const wf_server_opts*, wf_server**) { return WF_EUNSUPPORTED; }
-extern "C" wf_status wf_submit(wf_server*, const wf_request*, uint64_t*) { return WF_EUNSUPPORTED; }
-extern "C" wf_status wf_poll(wf_server*, uint64_t, wf_result*) { return WF_EUNSUPPORTED; }
-extern "C" wf_status wf_release(wf_server*, uint64_t) { return WF_EUNSUPPORTED; }
-extern "C" wf_status wf_server_destroy(wf_server*) { return WF_EUNSUPPORTED; }
-extern "C" wf_status wf_server_memory(wf_server*, int64_t*, int64_t*) { return WF_EUNSUPPORTED; }
+using namespace wfk;
+using namespace wfh;
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr size_t ALIGN = 256;
+size_t round_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// First-fit allocator over one device allocation, with coalescing on release.
+class Arena {
+ public:
+  wf_status init(size_t bytes) {
+    size_ = round_up(bytes);
+    if (hipMalloc(&base_, size_) != hipSuccess) {
+      base_ = nullptr;
+      return fail(WF_ENOMEM, "cannot allocate the server's device memory budget");
+    }
+    free_[0] = size_;
+    return WF_OK;
+  }
+  void destroy() {
+    if (base_) hipFree(base_);
+    base_ = nullptr;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = round_up(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t at = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      in_use_ += bytes;
+      peak_ = std::max(peak_, in_use_);
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = round_up(bytes);
+    in_use_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  char* base() const { return (char*)base_; }
+  size_t size() const { return size_; }
+  size_t in_use() const { return in_use_; }
+  size_t peak() const { return peak_; }
+
+ private:
+  void* base_ = nullptr;
+  size_t size_ = 0, in_use_ = 0, peak_ = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+};
+
+enum ReqState { QUEUED, ADMITTED, LAUNCHED, DONE, FAILED };
+
+struct Req {
+  wf_request r;
+  ReqState state = QUEUED;
+  wf_status err = WF_OK;
+  std::string msg;
+  double t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
+  // Server memory: one arena block holding, in order, the input copy (host
+  // inputs only), the full output (FULL mode), last row, last column, final
+  // cell and the handoff rows.
+  size_t off = 0, bytes = 0;
+  bool has_block = false;
+  const void* in = nullptr;
+  int64_t ld_in = 0;
+  void* out = nullptr;
+  void* last_row = nullptr;
+  void* last_col = nullptr;
+  void* final_cell = nullptr;
+  uint32_t* hand = nullptr;
+  size_t hand_n = 0;
+};
+
+// Byte layout of a request's block.
+struct Layout {
+  size_t in = 0, out = 0, last_row = 0, last_col = 0, final_cell = 0, hand = 0, total = 0;
+  size_t hand_n = 0;
+};
+
+Layout layout_of(const wf_request& r) {
+  Layout L;
+  size_t at = 0;
+  const size_t m = (size_t)r.m, n = (size_t)r.n;
+  if (r.input_kind == WF_INPUT_HOST) {
+    L.in = at;
+    at += round_up(m * n * 4);
+  }
+  if (r.mode == WF_MODE_FULL) {
+    L.out = at;
+    at += round_up(m * n * 4);
+  }
+  L.last_row = at;
+  at += round_up(n * 4);
+  L.last_col = at;
+  at += round_up(m * 4);
+  L.final_cell = at;
+  at += ALIGN;
+  // Handoff rows for the finest banding (64 rows per band), so any launch width fits.
+  const int64_t nb = (r.m + 63) / 64;
+  L.hand_n = nb > 1 ? (size_t)(nb - 1) * (size_t)hand_ld_for(r.n) : 0;
+  L.hand = at;
+  at += round_up(std::max<size_t>(L.hand_n, 1) * 4);
+  L.total = at;
+  return L;
+}
+
+// Everything one in-flight launch owns.
+struct LaunchSlot {
+  hipStream_t stream = nullptr;
+  uint32_t* ctl = nullptr;
+  GridDesc* d_grids = nullptr;
+  Item* d_items = nullptr;
+  size_t grids_cap = 0, items_cap = 0;
+  GridDesc* h_grids = nullptr;  // pinned staging, valid until `done` fires
+  Item* h_items = nullptr;
+  size_t h_grids_cap = 0, h_items_cap = 0;
+  uint32_t* host_err = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  std::vector<uint64_t> tickets;
+};
+
+template <class T>
+wf_status grow_dev(T** p, size_t* cap, size_t need) {
+  if (*cap >= need) return WF_OK;
+  if (*p) hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  const size_t c = std::max<size_t>(need, 256);
+  if (hipMalloc(p, c * sizeof(T)) != hipSuccess) return fail(WF_ENOMEM, "cannot allocate a launch table");
+  *cap = c;
+  return WF_OK;
+}
+
+template <class T>
+wf_status grow_host(T** p, size_t* cap, size_t need) {
+  if (*cap >= need) return WF_OK;
+  if (*p) hipHostFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  const size_t c = std::max<size_t>(need, 256);
+  if (hipHostMalloc((void**)p, c * sizeof(T), hipHostMallocDefault) != hipSuccess)
+    return fail(WF_ENOMEM, "cannot allocate pinned staging");
+  *cap = c;
+  return WF_OK;
+}
+
+}  // namespace
+
+struct wf_server {
+  wf_ctx* ctx = nullptr;
+  wf_server_opts opts{};
+  Arena arena;
+  std::vector<LaunchSlot> slots;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::thread thread;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  std::unordered_map<uint64_t, Req> reqs;
+  std::deque<uint64_t> queue;     // submitted, not admitted (arrival order)
+  std::deque<uint64_t> admitted;  // admitted, not launched
+  int inflight = 0;
+  uint64_t epoch = 0;             // bumped by every submit, release and stop
+  std::string thread_error;       // a HIP failure inside the server thread
+
+  void run();
+  void retire(LaunchSlot& L, double t);
+  void admit(double t);
+  bool launch_one(std::unique_lock<std::mutex>& lk);
+  wf_status enqueue(LaunchSlot& L, std::vector<Req*>& batch, int W, int dtype, int rule);
+};
+
+void wf_server::retire(LaunchSlot& L, double t) {
+  const bool timed_out = *L.host_err != DEV_OK;
+  *L.host_err = DEV_OK;
+  for (uint64_t tk : L.tickets) {
+    auto it = reqs.find(tk);
+    if (it == reqs.end()) continue;
+    Req& q = it->second;
+    q.t_done = t;
+    if (timed_out) {
+      q.state = FAILED;
+      q.err = WF_ETIMEDOUT;
+      q.msg = "device watchdog fired in the request's launch";
+    } else {
+      q.state = DONE;
+    }
+  }
+  L.tickets.clear();
+  L.busy = false;
+  --inflight;
+}
+
+void wf_server::admit(double t) {
+  while (!queue.empty()) {
+    Req& q = reqs[queue.front()];
+    size_t off = 0;
+    if (!arena.alloc(q.bytes, &off)) break;  // wait for memory: admission stays in arrival order
+    const Layout Lo = layout_of(q.r);
+    char* b = arena.base() + off;
+    q.off = off;
+    q.has_block = true;
+    if (q.r.input_kind == WF_INPUT_HOST) {
+      q.in = b + Lo.in;
+      q.ld_in = q.r.n;
+    } else {
+      q.in = q.r.input;
+      q.ld_in = q.r.ld_input;
+    }
+    q.out = q.r.mode == WF_MODE_FULL ? (void*)(b + Lo.out) : nullptr;
+    q.last_row = b + Lo.last_row;
+    q.last_col = b + Lo.last_col;
+    q.final_cell = b + Lo.final_cell;
+    q.hand = (uint32_t*)(b + Lo.hand);
+    q.hand_n = Lo.hand_n;
+    q.state = ADMITTED;
+    q.t_admit = t;
+    admitted.push_back(queue.front());
+    queue.pop_front();
+  }
+}
+
+wf_status wf_server::enqueue(LaunchSlot& L, std::vector<Req*>& batch, int W, int dtype, int rule) {
+  hipStream_t s = L.stream;
+  // Inputs and handoff rows.
+  const uint32_t sent = sentinel_of(dtype);
+  for (Req* q : batch) {
+    if (q->r.input_kind == WF_INPUT_HOST)
+      WF_HIP(hipMemcpy2DAsync((void*)q->in, (size_t)q->ld_in * 4, q->r.input, (size_t)q->r.ld_input * 4,
+                              (size_t)q->r.n * 4, (size_t)q->r.m, hipMemcpyHostToDevice, s));
+    if (q->hand_n) WF_HIP(launch_fill_u32(q->hand, sent, (int64_t)q->hand_n, s));
+  }
+  // Descriptors, largest grid first, and the grid-major work list.
+  std::sort(batch.begin(), batch.end(), [](const Req* a, const Req* b) { return a->r.m * a->r.n > b->r.m * b->r.n; });
+  size_t nitems = 0;
+  for (Req* q : batch) nitems += (size_t)((q->r.m + 64 * W - 1) / (64 * W));
+  wf_status st = grow_host(&L.h_grids, &L.h_grids_cap, batch.size());
+  if (st == WF_OK) st = grow_host(&L.h_items, &L.h_items_cap, nitems);
+  if (st == WF_OK) st = grow_dev(&L.d_grids, &L.grids_cap, batch.size());
+  if (st == WF_OK) st = grow_dev(&L.d_items, &L.items_cap, nitems);
+  if (st != WF_OK) return st;
+  size_t k = 0;
+  for (size_t gi = 0; gi < batch.size(); ++gi) {
+    const Req* q = batch[gi];
+    wf_problem p;
+    std::memset(&p, 0, sizeof p);
+    p.m = q->r.m;
+    p.n = q->r.n;
+    p.dtype = q->r.dtype;
+    p.rule = q->r.rule;
+    p.mode = q->r.mode;
+    p.cost = q->in;
+    p.ld_cost = q->ld_in;
+    p.out = q->out;
+    p.ld_out = q->r.n;
+    p.last_row = q->last_row;
+    p.last_col = q->last_col;
+    p.final_cell = q->final_cell;
+    GridDesc d = make_desc(&p, W, q->hand);
+    L.h_grids[gi] = d;
+    for (int b = 0; b < d.nbands; ++b) L.h_items[k++] = Item{(uint32_t)gi, (uint32_t)b};
+  }
+  WF_HIP(hipMemcpyAsync(L.d_grids, L.h_grids, batch.size() * sizeof(GridDesc), hipMemcpyHostToDevice, s));
+  WF_HIP(hipMemcpyAsync(L.d_items, L.h_items, nitems * sizeof(Item), hipMemcpyHostToDevice, s));
+  KArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.grids = L.d_grids;
+  a.items = L.d_items;
+  a.nitems = (int64_t)nitems;
+  a.ctl = L.ctl;
+  a.watchdog_ticks = ctx->watchdog_ticks;
+  const int nwg = (int)std::min<int64_t>((int64_t)nitems, (int64_t)ctx->num_cus * wgs_per_cu(W));
+  WF_HIP(launch_fill_u32(L.ctl, 0u, CTL_WORDS, s));
+  WF_HIP(launch_sweep(dtype, rule, W, nwg, a, s));
+  WF_HIP(hipMemcpyAsync(L.host_err, L.ctl + CTL_ERROR, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  WF_HIP(hipEventRecord(L.done, s));
+  return WF_OK;
+}
+
+// Launch the admitted requests that share the oldest one's dtype and rule, if a
+// stream is free.  Called with the lock held; drops it around the HIP calls.
+bool wf_server::launch_one(std::unique_lock<std::mutex>& lk) {
+  if (admitted.empty()) return false;
+  LaunchSlot* L = nullptr;
+  for (auto& s : slots)
+    if (!s.busy) {
+      L = &s;
+      break;
+    }
+  if (!L) return false;
+  const Req& first = reqs[admitted.front()];
+  const int dtype = first.r.dtype, rule = first.r.rule;
+  std::vector<Req*> batch;
+  std::vector<uint64_t> tickets;
+  int64_t max_m = 1;
+  for (auto it = admitted.begin(); it != admitted.end() && (int)batch.size() < opts.max_batch;) {
+    Req& q = reqs[*it];
+    if (q.r.dtype == dtype && q.r.rule == rule) {
+      batch.push_back(&q);
+      tickets.push_back(*it);
+      max_m = std::max(max_m, q.r.m);
+      q.state = LAUNCHED;
+      it = admitted.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  L->busy = true;
+  L->tickets = tickets;
+  ++inflight;
+  const int W = choose_waves(max_m / 2 > 0 ? max_m / 2 : 1);
+  const double t = now_s();
+  for (Req* q : batch) q->t_launch = t;
+  // Requests in `batch` are LAUNCHED: wf_release refuses them, so the pointers stay valid.
+  lk.unlock();
+  wf_status st = enqueue(*L, batch, W, dtype, rule);
+  const std::string msg = st == WF_OK ? std::string() : std::string(wf_last_error());
+  lk.lock();
+  if (st != WF_OK) {
+    for (uint64_t tk : tickets) {
+      Req& q = reqs[tk];
+      q.state = FAILED;
+      q.err = st;
+      q.msg = msg;
+      q.t_done = now_s();
+    }
+    // Nothing may still run on the stream before the slot is reused.
+    hipStreamSynchronize(L->stream);
+    L->tickets.clear();
+    L->busy = false;
+    --inflight;
+    thread_error = msg;
+  }
+  return true;
+}
+
+void wf_server::run() {
+  hipSetDevice(ctx->device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    const double t = now_s();
+    for (auto& L : slots)
+      if (L.busy && hipEventQuery(L.done) == hipSuccess) retire(L, t);
+    if (!stop) admit(t);
+    bool launched = false;
+    while (!stop && launch_one(lk)) launched = true;
+    if (stop && inflight == 0) break;
+    if (launched) continue;
+    const uint64_t seen = epoch;
+    if (inflight > 0) {
+      // Launches in flight: look at their events again shortly, or at once on a submit.
+      cv.wait_for(lk, std::chrono::microseconds(20), [&] { return stop || epoch != seen; });
+    } else {
+      // Idle (or waiting for memory held by finished requests): sleep until something changes.
+      cv.wait(lk, [&] { return stop || epoch != seen; });
+    }
+  }
+}
+
+// ------------------------------------------------------------------ public
+extern "C" wf_status wf_server_create(wf_ctx* ctx, const wf_server_opts* opts, wf_server** out) {
+  if (!ctx || !out) return fail(WF_EINVAL, "ctx and out must not be NULL");
+  *out = nullptr;
+  wf_server_opts o;
+  std::memset(&o, 0, sizeof o);
+  if (opts) o = *opts;
+  for (int i = 0; i < 4; ++i)
+    if (o.reserved[i] != 0) return fail(WF_EINVAL, "wf_server_opts.reserved must be 0");
+  if (o.hbm_budget_bytes < 0 || o.max_inflight < 0 || o.max_batch < 0) return fail(WF_EINVAL, "negative option");
+  if (o.hbm_budget_bytes == 0) o.hbm_budget_bytes = (int64_t)64 << 30;
+  if (o.max_inflight == 0) o.max_inflight = 4;
+  if (o.max_batch == 0) o.max_batch = 256;
+  if (o.max_inflight > 32) return fail(WF_EINVAL, "max_inflight above 32");
+  wf_status st = set_device(ctx);
+  if (st != WF_OK) return st;
+  std::unique_ptr<wf_server> s(new wf_server);
+  s->ctx = ctx;
+  s->opts = o;
+  st = s->arena.init((size_t)o.hbm_budget_bytes);
+  if (st != WF_OK) return st;
+  s->slots.resize((size_t)o.max_inflight);
+  for (auto& L : s->slots) {
+    WF_HIP(hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
+    WF_HIP(hipMalloc(&L.ctl, CTL_WORDS * sizeof(uint32_t)));
+    WF_HIP(hipHostMalloc((void**)&L.host_err, sizeof(uint32_t), hipHostMallocDefault));
+    *L.host_err = DEV_OK;
+    WF_HIP(hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
+  }
+  wf_server* raw = s.get();
+  s->thread = std::thread([raw] { raw->run(); });
+  *out = s.release();
+  return WF_OK;
+}
+
+extern "C" wf_status wf_submit(wf_server* s, const wf_request* r, uint64_t* ticket) {
+  if (!s || !r || !ticket) return fail(WF_EINVAL, "server, request and ticket must not be NULL");
+  if (r->m < 0 || r->n < 0) return fail(WF_EINVAL, "m and n must be >= 0");
+  if (r->dtype != WF_F32 && r->dtype != WF_I32) return fail(WF_EINVAL, "unknown dtype");
+  if (r->rule != WF_RULE_MIN && r->rule != WF_RULE_MAX) return fail(WF_EINVAL, "unknown rule");
+  if (r->mode != WF_MODE_FULL && r->mode != WF_MODE_EDGES) return fail(WF_EINVAL, "unknown mode");
+  if (r->input_kind != WF_INPUT_DEVICE && r->input_kind != WF_INPUT_HOST)
+    return fail(WF_EINVAL, "unknown input kind");
+  const bool empty = r->m == 0 || r->n == 0;
+  if (!empty && (!r->input || r->ld_input < r->n)) return fail(WF_EINVAL, "input is NULL or ld_input < n");
+  if (r->n > ((int64_t)1 << 28)) return fail(WF_EUNSUPPORTED, "n above 2^28 is not supported");
+  Req q;
+  q.r = *r;
+  q.t_submit = now_s();
+  if (!empty) {
+    q.bytes = layout_of(*r).total;
+    if (q.bytes > s->arena.size()) return fail(WF_E2BIG, "the request can never fit the server's memory budget");
+  }
+  std::lock_guard<std::mutex> g(s->mu);
+  if (s->stop) return fail(WF_ESHUTDOWN, "server is shutting down");
+  const uint64_t t = s->next_ticket++;
+  if (empty) {
+    q.state = DONE;
+    q.t_admit = q.t_launch = q.t_done = q.t_submit;
+    s->reqs.emplace(t, std::move(q));
+  } else {
+    s->reqs.emplace(t, std::move(q));
+    s->queue.push_back(t);
+    ++s->epoch;
+    s->cv.notify_one();
+  }
+  *ticket = t;
+  return WF_OK;
+}
+
+extern "C" wf_status wf_poll(wf_server* s, uint64_t ticket, wf_result* out) {
+  if (!s || !out) return fail(WF_EINVAL, "server and out must not be NULL");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(WF_ENOTFOUND, "unknown or released ticket");
+  const Req& q = it->second;
+  if (q.state == FAILED) return fail(q.err, q.msg);
+  if (q.state != DONE) return WF_PENDING;
+  std::memset(out, 0, sizeof *out);
+  out->out = q.out;
+  out->ld_out = q.out ? q.r.n : 0;
+  out->last_row = q.last_row;
+  out->last_col = q.last_col;
+  out->final_cell = q.final_cell;
+  out->t_submit = q.t_submit;
+  out->t_admit = q.t_admit;
+  out->t_launch = q.t_launch;
+  out->t_done = q.t_done;
+  return WF_OK;
+}
+
+extern "C" wf_status wf_release(wf_server* s, uint64_t ticket) {
+  if (!s) return fail(WF_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(WF_ENOTFOUND, "unknown or released ticket");
+  Req& q = it->second;
+  if (q.state == ADMITTED || q.state == LAUNCHED) return fail(WF_PENDING, "the request is still running");
+  if (q.state == QUEUED) s->queue.erase(std::find(s->queue.begin(), s->queue.end(), ticket));
+  if (q.has_block) s->arena.release(q.off, q.bytes);
+  s->reqs.erase(it);
+  ++s->epoch;
+  s->cv.notify_one();  // memory freed: admission may proceed
+  return WF_OK;
+}
+
+extern "C" wf_status wf_server_memory(wf_server* s, int64_t* in_use, int64_t* peak) {
+  if (!s) return fail(WF_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> g(s->mu);
+  if (in_use) *in_use = (int64_t)s->arena.in_use();
+  if (peak) *peak = (int64_t)s->arena.peak();
+  return WF_OK;
+}
+
+extern "C" wf_status wf_server_destroy(wf_server* s) {
+  if (!s) return WF_OK;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+    ++s->epoch;
+    // Requests not yet launched are cancelled; launched ones drain.
+    for (uint64_t t : s->queue) s->reqs.erase(t);
+    for (uint64_t t : s->admitted) s->reqs.erase(t);
+    s->queue.clear();
+    s->admitted.clear();
+    s->cv.notify_all();
+  }
+  if (s->thread.joinable()) s->thread.join();
+  set_device(s->ctx);
+  for (auto& L : s->slots) {
+    if (L.stream) {
+      hipStreamSynchronize(L.stream);
+      hipStreamDestroy(L.stream);
+    }
+    if (L.ctl) hipFree(L.ctl);
+    if (L.d_grids) hipFree(L.d_grids);
+    if (L.d_items) hipFree(L.d_items);
+    if (L.h_grids) hipHostFree(L.h_grids);
+    if (L.h_items) hipHostFree(L.h_items);
+    if (L.host_err) hipHostFree(L.host_err);
+    if (L.done) hipEventDestroy(L.done);
+  }
+  s->arena.destroy();
+  delete s;
+  return WF_OK;
+}

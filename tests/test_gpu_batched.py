@@ -1,0 +1,115 @@
+"""GPU parity of the batched sweep: many uneven grids in one persistent launch.
+
+Every grid of a batch must be bit-identical to the CPU oracle (fp32 / int32),
+for every configuration the autotuner can pick (waves per workgroup 1, 2, 4;
+grid-major and interleaved work order), on graph replay, and in edges mode.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_2501_05938_amd as wf  # noqa: E402
+import wfgen  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def _batch(count, lo, hi, dtype="f32", seed=4):
+    shapes = wfgen.batch_shapes(count, lo=lo, hi=hi, seed=seed)
+    hs = [wfgen.cells(wfgen.batch_seed(g), m, n, dtype) for g, (m, n) in enumerate(shapes)]
+    return shapes, hs, [torch.from_numpy(h).to(DEV) for h in hs]
+
+
+def _expect(h, rule, dtype):
+    if dtype == "f32":
+        return oracle.sweep(h, rule, "f32").view(np.uint32)
+    return oracle.sweep(h, rule, "i64").astype(np.int32)
+
+
+def _bits(t):
+    a = t.cpu().numpy()
+    return a.view(np.uint32) if a.dtype == np.float32 else a
+
+
+@pytest.mark.parametrize("W", [1, 2, 4])
+@pytest.mark.parametrize("order", [1, 2])
+def test_every_configuration(W, order):
+    print(f"[batched] W={W} order={order}", flush=True)
+    shapes, hs, ds = _batch(40, 1, 700, seed=11)
+    outs = wf.solve_batched(ds, waves_per_wg=W, order=order, use_graph=0)
+    torch.cuda.synchronize()
+    wf.check()
+    for (m, n), h, o in zip(shapes, hs, outs):
+        assert np.array_equal(_bits(o), _expect(h, "min", "f32")), (m, n, W, order)
+
+
+def test_autotuned_graph_replay_and_alone():
+    """Autotuned, captured once, replayed twice; each grid equals the grid swept alone."""
+    shapes, hs, ds = _batch(64, 64, 1024, seed=12)
+    outs = [torch.full_like(d, float("nan")) for d in ds]
+    for rep in range(3):
+        print(f"[batched] autotuned replay {rep}", flush=True)
+        for o in outs:
+            o.fill_(float("nan"))
+        wf.solve_batched(ds, outs)
+        torch.cuda.synchronize()
+        wf.check()
+        for (m, n), h, d, o in zip(shapes, hs, ds, outs):
+            if rep == 0:
+                assert np.array_equal(_bits(o), _expect(h, "min", "f32")), (m, n)
+            else:
+                assert torch.equal(o, wf.solve(d)), (m, n, rep)
+
+
+@pytest.mark.parametrize("rule", ["min", "max"])
+def test_int32_batch(rule):
+    shapes, hs, ds = _batch(24, 1, 600, dtype="i32", seed=13)
+    outs = wf.solve_batched(ds, rule=rule, use_graph=0)
+    torch.cuda.synchronize()
+    for (m, n), h, o in zip(shapes, hs, outs):
+        assert np.array_equal(_bits(o), _expect(h, rule, "i32")), (m, n, rule)
+
+
+def test_edges_batch():
+    shapes, hs, ds = _batch(24, 1, 900, seed=14)
+    outs = wf.solve_batched(ds, mode="edges", use_graph=0)
+    torch.cuda.synchronize()
+    for (m, n), h, (lr, lc, fc) in zip(shapes, hs, outs):
+        exp = oracle.sweep(h, "min", "f32")
+        assert np.array_equal(_bits(lr), exp[-1].view(np.uint32)), (m, n)
+        assert np.array_equal(_bits(lc), exp[:, -1].view(np.uint32)), (m, n)
+        assert _bits(fc)[0] == exp[-1, -1].view(np.uint32)
+
+
+def test_mixed_dtype_batch_is_rejected():
+    a = torch.zeros((4, 4), dtype=torch.float32, device=DEV)
+    b = torch.zeros((4, 4), dtype=torch.int32, device=DEV)
+    with pytest.raises(wf.WfError) as e:
+        wf.solve_batched([a, b])
+    assert e.value.status == -8  # WF_EUNSUPPORTED
+
+
+@pytest.mark.slow
+def test_benchmark_batch_sampled():
+    """The 4096-grid benchmark batch (sizes log-uniform in [64, 2048]) as the benchmark
+    launches it; 48 sampled grids compared with the oracle."""
+    shapes = wfgen.batch_shapes(4096)
+    ds = []
+    for g, (m, n) in enumerate(shapes):
+        t = torch.empty((m, n), dtype=torch.float32, device=DEV)
+        wfgen.fill_device(t, seed=wfgen.batch_seed(g))
+        ds.append(t)
+    outs = wf.solve_batched(ds)
+    torch.cuda.synchronize()
+    wf.check()
+    rng = np.random.default_rng(3)
+    for g in sorted(rng.choice(len(shapes), 48, replace=False)):
+        m, n = shapes[g]
+        h = wfgen.cells(wfgen.batch_seed(g), m, n, "f32")
+        assert np.array_equal(_bits(outs[g]), _expect(h, "min", "f32")), (g, m, n)

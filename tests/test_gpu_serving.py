@@ -1,0 +1,132 @@
+"""GPU tests of the serving front end (wf_server_* through the C ABI).
+
+Each served result must be bit-identical to the same grid swept alone with
+wf_solve (and, for a few, to the CPU oracle): admission, batching with other
+requests and overlap with other launches must not change a single bit.
+"""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_2501_05938_amd as wf  # noqa: E402
+import wfgen  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def _wait_all(srv, tickets, timeout_s=60.0):
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets):
+        for t in tickets:
+            if t not in done:
+                r = srv.poll(t)
+                if r is not None:
+                    done[t] = r
+        if time.time() - t0 > timeout_s:
+            raise TimeoutError(f"{len(tickets) - len(done)} requests still pending")
+        time.sleep(0.0005)
+    return done
+
+
+def _bits(t):
+    a = t.cpu().numpy()
+    return a.view(np.uint32) if a.dtype == np.float32 else a
+
+
+def test_mix_equals_alone():
+    """Requests of mixed size, dtype, rule, mode and input kind, submitted together."""
+    rng = np.random.default_rng(7)
+    specs = []
+    for q in range(24):
+        m = int(rng.integers(1, 700))
+        n = int(rng.integers(1, 900))
+        dt = "f32" if q % 3 else "i32"
+        rule = "min" if q % 4 else "max"
+        mode = "full" if q % 5 else "edges"
+        host = q % 2 == 1
+        specs.append((m, n, dt, rule, mode, host, 60000 + q))
+    print(f"[serving] mix of {len(specs)} requests", flush=True)
+    inputs, tickets = [], []
+    with wf.Server(budget_bytes=1 << 30, max_inflight=4, max_batch=8) as srv:
+        for (m, n, dt, rule, mode, host, seed) in specs:
+            c = wfgen.cells(seed, m, n, dt)
+            x = c if host else torch.from_numpy(c).to(DEV)
+            inputs.append(c)
+            tickets.append(srv.submit(x, rule=rule, mode=mode))
+            # keep device inputs alive: the server holds a reference until release
+        torch.cuda.synchronize()
+        res = _wait_all(srv, tickets)
+        for (m, n, dt, rule, mode, host, seed), c, t in zip(specs, inputs, tickets):
+            r = res[t]
+            alone = wf.solve(torch.from_numpy(c).to(DEV), rule=rule)
+            torch.cuda.synchronize()
+            exp = _bits(alone)
+            if mode == "full":
+                assert np.array_equal(_bits(r["out"]), exp), (m, n, dt, rule, mode)
+            assert np.array_equal(_bits(r["last_row"]), exp[-1]), (m, n, dt, rule, mode)
+            assert np.array_equal(_bits(r["last_col"]), exp[:, -1]), (m, n, dt, rule, mode)
+            assert _bits(r["final_cell"])[0] == exp[-1, -1]
+            assert r["t_submit"] <= r["t_admit"] <= r["t_launch"] <= r["t_done"]
+            srv.release(t)
+        assert srv.memory()[0] == 0
+    wf.check()
+
+
+def test_served_result_matches_oracle():
+    c = wfgen.cells(61, 300, 513, "f32")
+    with wf.Server(budget_bytes=64 << 20) as srv:
+        t = srv.submit(c)  # host input, copied in at admission
+        r = _wait_all(srv, [t])[t]
+        got = _bits(r["out"])
+        srv.release(t)
+    assert np.array_equal(got, oracle.sweep(c, "min", "f32").view(np.uint32))
+
+
+def test_budget_limits_admission():
+    """A budget that holds only a few requests at once: all complete, the peak stays
+    within the budget, and memory returns to zero after release."""
+    m = n = 512
+    per = m * n * 4 * 2  # output + rounding slack per request, roughly
+    budget = 3 * per
+    with wf.Server(budget_bytes=budget, max_inflight=2, max_batch=4) as srv:
+        cs = [torch.from_numpy(wfgen.cells(70 + q, m, n, "f32")).to(DEV) for q in range(10)]
+        tickets = [srv.submit(c) for c in cs]
+        pending = set(tickets)
+        t0 = time.time()
+        while pending:
+            for t in list(pending):
+                r = srv.poll(t)
+                if r is not None:
+                    exp = wf.solve(cs[tickets.index(t)])
+                    torch.cuda.synchronize()
+                    assert torch.equal(r["out"], exp)
+                    srv.release(t)  # frees memory so later requests are admitted
+                    pending.discard(t)
+            assert time.time() - t0 < 60, "admission stalled"
+            time.sleep(0.0005)
+        in_use, peak = srv.memory()
+        assert in_use == 0
+        assert 0 < peak <= budget
+
+
+def test_oversized_and_invalid_requests():
+    with wf.Server(budget_bytes=1 << 20) as srv:
+        with pytest.raises(wf.WfError) as e:
+            srv.submit(torch.zeros((1024, 1024), dtype=torch.float32, device=DEV))
+        assert e.value.status == -3  # WF_E2BIG
+        with pytest.raises(wf.WfError) as e:
+            srv.poll(12345)
+        assert e.value.status == -6  # WF_ENOTFOUND
+        t = srv.submit(torch.zeros((0, 5), dtype=torch.float32, device=DEV))
+        r = srv.poll(t)
+        assert r is not None and r["out"] is None
+        srv.release(t)
