@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--serve-grids", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="run one plain 1 GiB device-to-device copy first: a kernel of known HBM "
+                         "traffic (1 GiB read + 1 GiB written) to scale memory counters by")
     return ap.parse_args()
 
 
@@ -248,6 +251,15 @@ def main():
     out = torch.empty((M, N), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
 
+    if args.copy_ref:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] reference copy: 1 GiB read + 1 GiB written")
     log(f"[bench] warmup {args.warmup}")
     for _ in range(args.warmup):
         wf.solve(cost, out=out)

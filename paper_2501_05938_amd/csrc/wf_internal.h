@@ -46,12 +46,14 @@ struct KArgs {
 //   [5] cycles waiting for top-boundary quads   [6] loader cycles waiting for a free c slot
 //   [7] wall clock (100 MHz) at band start
 constexpr int TRACE_WORDS = 8;
-// Per-chunk trace record (compute waves, when KArgs::ctrace is set):
+// Per-chunk trace record (compute waves, when KArgs::ctrace is set; chunks
+// 0, CTRACE_EVERY, 2*CTRACE_EVERY, ...):
 //   [0] wall clock on reaching the chunk start   [1] wall clock when its wait ended
 //   [2] cycles spent so far waiting for top-boundary quads (needs KArgs::trace)
 //   [3] which conditions were not met on arrival: 1 c ring, 2 H ring, 4 own T ring,
 //       8 consumer's T ring
 constexpr int CTRACE_WORDS = 4;
+constexpr int CTRACE_EVERY = 8;   // one record per this many chunks
 
 // Control-word indices.
 enum { CTL_TICKET = 0, CTL_ERROR = 1, CTL_ABORT = 2, CTL_WORDS = 4 };

@@ -165,6 +165,30 @@ __device__ __forceinline__ void raise_abort(WaveLds* lds, const KArgs& a) {
   __hip_atomic_store(G32(a.ctl + CTL_ABORT), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Idle-time watchdog.  A clock read is a scalar-memory round trip (hundreds of
+// cycles), far longer than one poll, so the clock is read only once every
+// WATCH_SPINS idle polls: the first read starts the idle period, later ones
+// compare against it.  Progress resets the watch.
+constexpr uint32_t WATCH_SPINS = 1024;
+struct Watch {
+  uint64_t t0 = 0;
+  uint32_t spins = 0;
+  __device__ void reset() {
+    t0 = 0;
+    spins = 0;
+  }
+  // True once the current idle period has lasted longer than `ticks`.
+  __device__ bool tick(uint64_t ticks) {
+    if ((++spins & (WATCH_SPINS - 1)) != 0u) return false;
+    const uint64_t now = wall_clock64() | 1u;  // never 0
+    if (t0 == 0) {
+      t0 = now;
+      return false;
+    }
+    return now - t0 > ticks;
+  }
+};
+
 // Spin until cond() holds.  Returns false (without waiting further) if the launch is
 // aborting; callers then run on to the end of the band, whose output is discarded.
 // Compute waves watch only the workgroup flag (no global loads on their path, so the
@@ -173,7 +197,7 @@ __device__ __forceinline__ void raise_abort(WaveLds* lds, const KArgs& a) {
 template <bool DEVICE_FLAG, class F>
 __device__ __forceinline__ bool wait_until(F&& cond, WaveLds* lds, const KArgs& a) {
   if (cond()) return true;
-  const uint64_t t0 = wall_clock64();
+  Watch w;
   uint32_t polls = 0;
   for (;;) {
     __builtin_amdgcn_s_sleep(1);
@@ -183,7 +207,10 @@ __device__ __forceinline__ bool wait_until(F&& cond, WaveLds* lds, const KArgs& 
       st_ctl(&lds[0].abort, 1u);
       return false;
     }
-    if (wall_clock64() - t0 > a.watchdog_ticks) { raise_abort(lds, a); return false; }
+    if (w.tick(a.watchdog_ticks)) {
+      raise_abort(lds, a);
+      return false;
+    }
   }
 }
 
@@ -201,17 +228,20 @@ __device__ __forceinline__ bool aborting(WaveLds* lds, uint32_t* ctl, uint64_t w
   return false;
 }
 
-// Called every few thousand spins of an inline wait: true when the wait should end
-// (launch aborting, or no progress for longer than the watchdog since t0).
-__device__ __noinline__ bool spin_expired(WaveLds* lds, uint32_t* ctl, uint64_t watchdog_ticks, uint64_t t0) {
-  if (ld_ctl(&lds[0].abort)) return true;
-  if (wall_clock64() - t0 > watchdog_ticks) {
+// Rare path of an inline spin, called every few thousand polls.  Returns the start
+// of the idle period (taking it now when t0 is 0), or 0 when the wait must end: the
+// launch is aborting, or the wait has outlasted the watchdog (then it raises the abort).
+__device__ __noinline__ uint64_t spin_check(WaveLds* lds, uint32_t* ctl, uint64_t watchdog_ticks, uint64_t t0) {
+  if (ld_ctl(&lds[0].abort)) return 0;
+  const uint64_t now = wall_clock64() | 1u;
+  if (t0 == 0) return now;
+  if (now - t0 > watchdog_ticks) {
     st_ctl(&lds[0].abort, 1u);
     __hip_atomic_store(G32(ctl + CTL_ERROR), (uint32_t)DEV_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(G32(ctl + CTL_ABORT), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
+    return 0;
   }
-  return false;
+  return t0;
 }
 
 // Spin until the T quad at `tp` has been written.  Returns false if the launch is aborting.
@@ -241,8 +271,12 @@ __device__ __forceinline__ void compute_chunk(
     u4 (&cq)[4], u4 (&tq)[4], uint32_t& tprev_w, T& H, T& Np, const KArgs& a, uint64_t* crec) {
   const uint32_t SENT = Num<T>::SENT;
   const int pos = CHUNK * k;
+  // Per-chunk records are sampled (every CTRACE_EVERY-th chunk): each clock read is a
+  // scalar-memory round trip that would otherwise slow the walk being measured.
   __attribute__((address_space(1))) uint64_t* rec =
-      crec ? (__attribute__((address_space(1))) uint64_t*)(void*)(crec + (int64_t)k * CTRACE_WORDS) : nullptr;
+      crec && (k % CTRACE_EVERY) == 0
+          ? (__attribute__((address_space(1))) uint64_t*)(void*)(crec + (int64_t)(k / CTRACE_EVERY) * CTRACE_WORDS)
+          : nullptr;
   if (rec && lane == 0) rec[0] = wall_clock64();
   // Chunk start: publish progress, then wait until the c ring holds this chunk and the next
   // (reads run two groups ahead), the H slots are free, and the consumer's T slots are re-armed.
@@ -263,7 +297,7 @@ __device__ __forceinline__ void compute_chunk(
       return true;
     };
     if (!ready()) {
-      const uint64_t c0 = __builtin_readcyclecounter();
+      const uint64_t c0 = a.trace ? __builtin_readcyclecounter() : 0;
       if (rec && lane == 0) {
         rec[3] = ((int)ld_ctl(&L.c_ready) < need_c ? 1u : 0u) | ((int)ld_ctl(&L.h_done) < need_h ? 2u : 0u) |
                  ((int)ld_ctl(&L.t_reset) < need_own_t ? 4u : 0u) |
@@ -308,12 +342,12 @@ __device__ __forceinline__ void compute_chunk(
         const bool ahead = KIND == 1 || g + 1 < gT;
         const lds_u8* tw = ahead ? tp1 : tp;
         const uint64_t c0 = a.trace ? __builtin_readcyclecounter() : 0;
-        const uint64_t t0 = wall_clock64();
+        uint64_t t0 = 0;
         uint32_t spins = 0;
         u4 probe_q;
         do {
           probe_q = lds_ld4_fresh(tw);
-          if ((++spins & 2047u) == 0u && spin_expired(lds, a.ctl, a.watchdog_ticks, t0)) break;
+          if ((++spins & 2047u) == 0u && (t0 = spin_check(lds, a.ctl, a.watchdog_ticks, t0)) == 0) break;
         } while (__builtin_amdgcn_readfirstlane(Num<T>::probe(probe_q)) == SENT);
         tq[q] = lds_ld4_fresh(tp);
         if (ahead) tq[(q + 1) & 3] = lds_ld4_fresh(tp1);
@@ -495,14 +529,14 @@ struct LoaderLanes {
 // Only waves that may load from memory (DEVICE_FLAG) poll the device-wide flag;
 // the others watch the workgroup flag, which those relay.
 template <bool DEVICE_FLAG>
-__device__ __forceinline__ bool io_idle(WaveLds* lds, const KArgs& a, uint64_t& t_idle, uint32_t& polls) {
+__device__ __forceinline__ bool io_idle(WaveLds* lds, const KArgs& a, Watch& w, uint32_t& polls) {
   __builtin_amdgcn_s_sleep(1);
   if (ld_ctl(&lds[0].abort)) return false;
   if (DEVICE_FLAG && (++polls & 255u) == 0u && ld_dev(a.ctl + CTL_ABORT)) {
     st_ctl(&lds[0].abort, 1u);
     return false;
   }
-  if (wall_clock64() - t_idle > a.watchdog_ticks) {
+  if (w.tick(a.watchdog_ticks)) {
     raise_abort(lds, a);
     return false;
   }
@@ -532,7 +566,7 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
   const uint32_t slot0 = (uint32_t)(uintptr_t)L8(L.cring);
   const int NC = B.NC;
   int issued = 0, committed = 0;
-  uint64_t t_idle = wall_clock64();
+  Watch t_idle;
   uint32_t polls = 0;
   for (;;) {
     // Issue every chunk whose slot the compute wave has released: slot k % C_SLOTS
@@ -580,7 +614,7 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
       CBAR();
       if (lane == 0) st_ctl(&L.c_ready, (uint32_t)(k + 1));
       ++committed;
-      t_idle = wall_clock64();
+      t_idle.reset();
       continue;
     }
     if (committed == NC) break;
@@ -654,7 +688,7 @@ __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds
       make_rsrc(g.hand + (band > 0 ? (int64_t)(band - 1) * g.hand_ld : 0), (uint32_t)(g.hand_ld * 4));
   int hr = 60;
   const int hand_end = B[0].T_END;
-  uint64_t t_idle = wall_clock64();
+  Watch t_idle;
   uint32_t polls = 0;
   for (;;) {
     bool did = false, done = true;
@@ -710,7 +744,7 @@ __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds
     }
     if (done) break;
     if (did) {
-      t_idle = wall_clock64();
+      t_idle.reset();
       continue;
     }
     if (!io_idle<false>(lds, a, t_idle, polls)) return;
@@ -727,7 +761,7 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
   __amdgpu_buffer_rsrc_t hand_in =
       make_rsrc(g.hand + (band > 0 ? (int64_t)(band - 1) * g.hand_ld : 0), (uint32_t)(g.hand_ld * 4));
   int tw = 60;
-  uint64_t t_idle = wall_clock64();
+  Watch t_idle;
   uint32_t polls = 0;
   while (tw < B.T_END) {
     int limit = (int)ld_ctl(&L.t_reset) + RING_T;
@@ -770,7 +804,7 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
       }
     }
     if (got) {
-      t_idle = wall_clock64();
+      t_idle.reset();
       continue;
     }
     if (!io_idle<true>(lds, a, t_idle, polls)) return;

@@ -304,7 +304,7 @@ extern "C" wf_status wf_solve(wf_ctx* ctx, const wf_problem* p, void* stream_) {
   uint64_t* trace = nullptr;
   const size_t trace_words = (size_t)a.nitems * W * TRACE_WORDS;
   // With WF_TRACE_CHUNKS=1 it also writes CTRACE_WORDS uint64 per (band, compute wave, chunk).
-  const int64_t nc = (4 * groups_for(p->n) + 15) / 16;
+  const int64_t nc = ((4 * groups_for(p->n) + 15) / 16 + CTRACE_EVERY - 1) / CTRACE_EVERY;
   const bool chunks = trace_file && *trace_file && std::getenv("WF_TRACE_CHUNKS");
   const size_t ctrace_words = chunks ? (size_t)a.nitems * W * (size_t)nc * CTRACE_WORDS : 0;
   uint64_t* ctrace = nullptr;
