@@ -206,16 +206,19 @@ def serving(torch, wf, wfgen, grids, requests, load):
         # results served in the mix equal the same grids swept alone
         checked = 0
         for g in range(min(4, grids)):
-            tk = srv.submit(costs[g])
-            for h in range(4):  # a few companions so the check runs inside a batch
-                srv.submit(costs[(g + h + 1) % grids])
-            while (r := srv.poll(tk)) is None:
+            tks = [srv.submit(costs[(g + h) % grids]) for h in range(5)]  # g with 4 companions
+            while any(srv.poll_times(t) is None for t in tks):
                 time.sleep(1e-4)
+            r = srv.poll(tks[0])
             alone = wf.solve(costs[g])
-            torch.cuda.synchronize()
-            if not torch.equal(r["out"], alone):
+            same = torch.equal(r["out"], alone)
+            torch.cuda.current_stream().synchronize()
+            if not same:
                 raise AssertionError(f"served grid {g} differs from the grid swept alone")
+            for t in tks:
+                srv.release(t)
             checked += 1
+    torch.cuda.synchronize()
     wf.check()
     lat = np.array(lat) * 1e3
     span = last_done - first_submit

@@ -85,13 +85,13 @@ enum { WF_RULE_MIN = 0, WF_RULE_MAX = 1 };    /* op of the cell rule */
 enum { WF_MODE_FULL = 0, WF_MODE_EDGES = 1 }; /* FULL writes all of H; EDGES writes only last row/col/cell */
 
 typedef struct wf_problem {
-  int64_t m, n;            /* grid rows and columns, >= 1 (0 means nothing to do) */
+  int64_t m, n;            /* grid rows and columns, >= 1 (0 means nothing to do); n <= 2^23 */
   int32_t dtype;           /* WF_F32 or WF_I32 */
   int32_t rule;            /* WF_RULE_MIN or WF_RULE_MAX */
   int32_t mode;            /* WF_MODE_FULL or WF_MODE_EDGES */
   int32_t flags;           /* must be 0 */
   const void* cost;        /* device, m x n, row stride ld_cost elements; required */
-  int64_t ld_cost;
+  int64_t ld_cost;         /* >= n and <= 2^23 (WF_EUNSUPPORTED above) */
   void* out;               /* device, m x n, row stride ld_out; required in FULL mode, ignored in EDGES */
   int64_t ld_out;
   const void* top;         /* device, n+1 values, or NULL for the default boundary */

@@ -94,6 +94,8 @@ template <> struct Num<float> {
     t = t > q.z ? t : q.z;
     return t > q.w ? t : q.w;
   }
+  // Probe of several quads from their probes.
+  __device__ static uint32_t combine(uint32_t a, uint32_t b) { return a > b ? a : b; }
   template <int RULE> __device__ static float absent() { return RULE == 0 ? __builtin_inff() : -__builtin_inff(); }
   template <int RULE> __device__ static float op3(float a, float b, float c) {
     if constexpr (RULE == 0) return __builtin_fminf(__builtin_fminf(a, b), c);
@@ -109,6 +111,7 @@ template <> struct Num<int32_t> {
     t = t < (int32_t)q.z ? t : (int32_t)q.z;
     return (uint32_t)(t < (int32_t)q.w ? t : (int32_t)q.w);
   }
+  __device__ static uint32_t combine(uint32_t a, uint32_t b) { return (int32_t)a < (int32_t)b ? a : b; }
   template <int RULE> __device__ static int32_t absent() { return RULE == 0 ? INT32_MAX : INT32_MIN + 1; }
   template <int RULE> __device__ static int32_t op3(int32_t a, int32_t b, int32_t c) {
     if constexpr (RULE == 0) { int32_t t = a < b ? a : b; return t < c ? t : c; }
@@ -260,15 +263,50 @@ __device__ __noinline__ u4 wait_quad(const lds_u8* tp, WaveLds* lds, uint32_t* c
   return q;
 }
 
-// One chunk (4 groups of 4 steps) of the walk.
-// KIND 0: the first four chunks, where lanes left of column 0 keep their boundary value
-//         and bounds are checked;  KIND 1: interior, no bounds checks;  KIND 2: tail.
-// CONS: 0 = no consumer, 1 = the next compute wave (LDS), 2 = the next band (global).
+// Reads of chunk kn's inputs for one lane: its four c quads and (groups below gT) its
+// four T quads.  A read past the last chunk only picks up unused stale data.
+template <int KIND>
+__device__ __forceinline__ void read_chunk(int kn, int gT, const lds_u8* crow, const lds_u8* tr_base,
+                                           u4 (&c)[4], u4 (&t)[4]) {
+  const lds_u8* cb = crow + (kn % C_SLOTS) * SLOT;
+  const int tpos = (CHUNK * kn + 64) & (RING_T - 1);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) c[q] = lds_ld4(cb + QUAD * q);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (KIND == 1 || 4 * kn + q < gT) t[q] = lds_ld4(tr_base + (tpos + 4 * q) * 4);
+}
+
+// Control words a chunk start checks, read ahead of time.  The counters only grow, so
+// a check that passes on values read earlier also passes on current ones; one that
+// fails falls back to waiting on fresh reads.
+struct CtlSnap {
+  uint32_t c_ready, h_done, t_reset, cons_t_reset;
+};
+
+template <int CONS>
+__device__ __forceinline__ void snap_ctl(WaveLds& L, WaveLds* C, CtlSnap& s) {
+  s.c_ready = ld_ctl(&L.c_ready);
+  s.h_done = ld_ctl(&L.h_done);
+  s.t_reset = ld_ctl(&L.t_reset);
+  s.cons_t_reset = CONS == 1 ? ld_ctl(&C->t_reset) : 0u;
+}
+
+// One chunk (4 groups of 4 steps) of the walk, computed from the inputs read during the
+// previous chunk (cc, tc) while the next chunk's inputs are read into (cn, tn).
+// The T quads of the chunk are validated together at its start (the group loop then runs
+// without branches): when the producer is not that far yet, the chunk waits for the
+// chunk's last quad, which the producer writes after the others.
+// KIND 0: the first four chunks, where lanes left of column 0 keep their boundary value;
+// KIND 1: interior (this chunk's and the next chunk's groups all lie below gT);
+// KIND 2: tail.  CONS: 0 = no consumer, 1 = the next compute wave (LDS), 2 = the next
+// band (global handoff row).
 template <typename T, int RULE, int KIND, int CONS>
 __device__ __forceinline__ void compute_chunk(
     int k, int G, int gT, int NCc, WaveLds* lds, WaveLds& L, WaveLds* C,
-    __amdgpu_buffer_rsrc_t hand_out, lds_u8* crow, lds_u8* hrow, lds_u8* ct_base, bool lane63, int lane,
-    u4 (&cq)[4], u4 (&tq)[4], uint32_t& tprev_w, T& H, T& Np, const KArgs& a, uint64_t* crec) {
+    __amdgpu_buffer_rsrc_t hand_out, const lds_u8* crow, lds_u8* hrow, lds_u8* ct_base, bool lane63, int lane,
+    const u4 (&cc)[4], u4 (&tc)[4], u4 (&cn)[4], u4 (&tn)[4], uint32_t& tprev_w, T& H, T& Np,
+    CtlSnap& snap, const KArgs& a, uint64_t* crec) {
   const uint32_t SENT = Num<T>::SENT;
   const int pos = CHUNK * k;
   // Per-chunk records are sampled (every CTRACE_EVERY-th chunk): each clock read is a
@@ -278,32 +316,28 @@ __device__ __forceinline__ void compute_chunk(
           ? (__attribute__((address_space(1))) uint64_t*)(void*)(crec + (int64_t)(k / CTRACE_EVERY) * CTRACE_WORDS)
           : nullptr;
   if (rec && lane == 0) rec[0] = wall_clock64();
-  // Chunk start: publish progress, then wait until the c ring holds this chunk and the next
-  // (reads run two groups ahead), the H slots are free, and the consumer's T slots are re-armed.
+  // Chunk start: publish progress, then wait until the c ring holds the next chunk, the
+  // H slot is free, this wave's T slots up to the next chunk's quads hold the current lap,
+  // and the consumer's T slots for this chunk are re-armed.
   CBAR();
   if (lane == 0) st_ctl(&L.progress, (uint32_t)pos);
   {
     const int need_c = k + 2 < NCc ? k + 2 : NCc;
     const int need_h = pos + CHUNK - H_SLOTS * CHUNK;
     const int need_t = pos + CHUNK - RING_T;
-    // This chunk reads T quads up to position pos + CHUNK + 8 + 64 (two groups ahead);
-    // their slots must no longer hold the previous lap's values.
-    const int need_own_t = pos + CHUNK + 8 + 64 - RING_T;
-    auto ready = [&] {
-      if ((int)ld_ctl(&L.c_ready) < need_c) return false;
-      if ((int)ld_ctl(&L.h_done) < need_h) return false;
-      if ((int)ld_ctl(&L.t_reset) < need_own_t) return false;
-      if (CONS == 1 && (int)ld_ctl(&C->t_reset) < need_t) return false;
-      return true;
+    const int need_own_t = pos + 2 * CHUNK + 64 - RING_T;
+    auto ok = [&](const CtlSnap& v) {
+      return (int)v.c_ready >= need_c && (int)v.h_done >= need_h && (int)v.t_reset >= need_own_t &&
+             (CONS != 1 || (int)v.cons_t_reset >= need_t);
     };
-    if (!ready()) {
+    if (!ok(snap)) {
       const uint64_t c0 = a.trace ? __builtin_readcyclecounter() : 0;
       if (rec && lane == 0) {
-        rec[3] = ((int)ld_ctl(&L.c_ready) < need_c ? 1u : 0u) | ((int)ld_ctl(&L.h_done) < need_h ? 2u : 0u) |
-                 ((int)ld_ctl(&L.t_reset) < need_own_t ? 4u : 0u) |
-                 (CONS == 1 && (int)ld_ctl(&C->t_reset) < need_t ? 8u : 0u);
+        rec[3] = ((int)snap.c_ready < need_c ? 1u : 0u) | ((int)snap.h_done < need_h ? 2u : 0u) |
+                 ((int)snap.t_reset < need_own_t ? 4u : 0u) |
+                 (CONS == 1 && (int)snap.cons_t_reset < need_t ? 8u : 0u);
       }
-      wait_until<false>(ready, lds, a);
+      wait_until<false>([&] { snap_ctl<CONS>(L, C, snap); return ok(snap); }, lds, a);
       if (a.trace && lane == 0) L.tr_chunk_wait += __builtin_readcyclecounter() - c0;
     }
     if (rec && lane == 0) {
@@ -312,51 +346,49 @@ __device__ __forceinline__ void compute_chunk(
     }
   }
   CBAR();
-  const int cs = k % C_SLOTS;
-  lds_u8* cb = crow + cs * SLOT;
-  lds_u8* cb_next = crow + (cs + 1 == C_SLOTS ? 0 : cs + 1) * SLOT;
-  lds_u8* hb = hrow + (k % H_SLOTS) * SLOT;
   const lds_u8* tr_base = L8(L.tring);
-  const int tpos = (pos + 64) & (RING_T - 1);             // T ring position of group 4k's quad
-  const int tpos_next = (pos + CHUNK + 64) & (RING_T - 1);
+  const int tpos = (pos + 64) & (RING_T - 1);  // T ring position of group 4k's quad
+  // Validate the chunk's T quads (those of groups below gT).  All four words of a quad
+  // are checked: a 16-byte LDS read racing a 16-byte write from another wave may see
+  // part of it.  All lanes read the same quads, so the test is wave-uniform.
+  if (KIND == 1 || 4 * k < gT) {
+    uint32_t pr = Num<T>::probe(tc[0]);
+#pragma unroll
+    for (int q = 1; q < 4; ++q)
+      if (KIND == 1 || 4 * k + q < gT) pr = Num<T>::combine(pr, Num<T>::probe(tc[q]));
+    if (__builtin_expect(__builtin_amdgcn_readfirstlane(pr) == SENT, 0)) {
+      // Wait (one lane polling) for the chunk's last quad below gT, then re-read them all.
+      int ql = 3;
+      if (KIND != 1)
+        while (ql > 0 && 4 * k + ql >= gT) --ql;
+      const lds_u8* tw = tr_base + (tpos + 4 * ql) * 4;
+      const uint64_t c0 = a.trace ? __builtin_readcyclecounter() : 0;
+      uint64_t t0 = 0;
+      uint32_t spins = 0;
+      for (;;) {
+        uint32_t p1 = SENT;
+        if (lane == 0) p1 = Num<T>::probe(lds_ld4_fresh(tw));
+        if (__builtin_amdgcn_readfirstlane(p1) != SENT) break;
+        if ((++spins & 2047u) == 0u && (t0 = spin_check(lds, a.ctl, a.watchdog_ticks, t0)) == 0) break;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (KIND == 1 || 4 * k + q < gT) tc[q] = lds_ld4_fresh(tr_base + (tpos + 4 * q) * 4);
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the re-read quads are in registers
+      if (a.trace && lane == 0) L.tr_t_wait += __builtin_readcyclecounter() - c0;
+    }
+  }
+  read_chunk<KIND == 1 ? 1 : 0>(k + 1, gT, crow, tr_base, cn, tn);
+  lds_u8* hb = hrow + (k % H_SLOTS) * SLOT;
   lds_u8* ct = ct_base + (pos & (RING_T - 1)) * 4;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int g = 4 * k + q;
     if (KIND == 2 && g >= G) break;
-    // 1. LDS reads of group g+2 (a read past the end only picks up unused stale data).
-    const int g2 = g + 2;
-    cq[(q + 2) & 3] = lds_ld4(q + 2 < 4 ? cb + QUAD * (q + 2) : cb_next + QUAD * (q - 2));
-    if (KIND == 1 || g2 < gT)
-      tq[(q + 2) & 3] = lds_ld4(tr_base + (q + 2 < 4 ? tpos + 4 * (q + 2) : tpos_next + 4 * (q - 2)) * 4);
-    // 2. The T quad of this group must have been written by the producer.
-    if (KIND == 1 || g < gT) {
-      // All four words are checked: a 16-byte LDS read racing a 16-byte write from another
-      // wave may see part of it.  All lanes read the same quad, so the test is wave-uniform.
-      if (__builtin_expect(__builtin_amdgcn_readfirstlane(Num<T>::probe(tq[q])) == SENT, 0)) {
-        // Miss: the producer is just ahead.  Wait for the NEXT quad as well, which leaves one
-        // group of slack so the following checks hit; the producer writes in order, so once
-        // quad g+1 is complete quad g is too.  Both are re-read.
-        const lds_u8* tp = tr_base + (tpos + 4 * q) * 4;
-        const lds_u8* tp1 = tr_base + (q + 1 < 4 ? tpos + 4 * (q + 1) : tpos_next + 4 * (q - 3)) * 4;
-        const bool ahead = KIND == 1 || g + 1 < gT;
-        const lds_u8* tw = ahead ? tp1 : tp;
-        const uint64_t c0 = a.trace ? __builtin_readcyclecounter() : 0;
-        uint64_t t0 = 0;
-        uint32_t spins = 0;
-        u4 probe_q;
-        do {
-          probe_q = lds_ld4_fresh(tw);
-          if ((++spins & 2047u) == 0u && (t0 = spin_check(lds, a.ctl, a.watchdog_ticks, t0)) == 0) break;
-        } while (__builtin_amdgcn_readfirstlane(Num<T>::probe(probe_q)) == SENT);
-        tq[q] = lds_ld4_fresh(tp);
-        if (ahead) tq[(q + 1) & 3] = lds_ld4_fresh(tp1);
-        if (a.trace && lane == 0) L.tr_t_wait += __builtin_readcyclecounter() - c0;
-      }
-    }
-    // 3. Four steps of the anti-diagonal walk.
-    const u4 cv = cq[q];
-    const u4 tv = tq[q];
+    // The next chunk start's checks, read while this last group runs.
+    if (q == 3) snap_ctl<CONS>(L, C, snap);
+    const u4 cv = cc[q];
+    const u4 tv = tc[q];
     const uint32_t tk[4] = {tprev_w, tv.x, tv.y, tv.z};
     if (KIND == 1 || g < gT) tprev_w = tv.w;
     u4 h4;
@@ -369,7 +401,7 @@ __device__ __forceinline__ void compute_chunk(
       H = Hn;
       h4[e] = bits(H);
     }
-    // 4. H into the ring, bottom row to the consumer.  Positions < 60 are never read by a consumer.
+    // H into the ring, bottom row to the consumer.  Positions < 60 are never read by a consumer.
     lds_st4(hb + QUAD * q, h4);
     if (CONS != 0 && (KIND != 0 || g >= 15)) {
       if (lane63) {
@@ -393,26 +425,34 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   if (a.trace && lane == 0) L.tr_first = __builtin_readcyclecounter();
   T Np = from_bits<T>(tprev.z);
   uint32_t tprev_w = tprev.w;
-  u4 cq[4], tq[4];
+  // Inputs of the current chunk and of the next one, in two register sets used in turn.
+  u4 cA[4], tA[4], cB[4], tB[4];
   wait_until<false>([&] { return ld_ctl(&L.c_ready) >= 1u; }, lds, a);
   CBAR();
-  cq[0] = lds_ld4(crow + 0);
-  cq[1] = lds_ld4(crow + QUAD);
-  cq[2] = cq[3] = cq[0];
-  tq[0] = lds_ld4(L8(L.tring) + 64 * 4);
-  tq[1] = lds_ld4(L8(L.tring) + 68 * 4);
-  tq[2] = tq[3] = tprev;
-
+  read_chunk<0>(0, gT, crow, L8(L.tring), cA, tA);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) tB[q] = tA[q];
+  CtlSnap snap;
+  snap_ctl<CONS>(L, C, snap);
+#define WF_CHUNK(KIND, KK, CUR_C, CUR_T, NXT_C, NXT_T)                                                        \
+  compute_chunk<T, RULE, KIND, CONS>(KK, G, gT, NCc, lds, L, C, hand_out, crow, hrow, ct_base, lane63, lane,  \
+                                     CUR_C, CUR_T, NXT_C, NXT_T, tprev_w, H, Np, snap, a, crec)
   int k = 0;
-  for (; k < 4; ++k)
-    compute_chunk<T, RULE, 0, CONS>(k, G, gT, NCc, lds, L, C, hand_out, crow, hrow, ct_base, lane63, lane,
-                                    cq, tq, tprev_w, H, Np, a, crec);
-  for (; 4 * k + 6 <= gT; ++k)
-    compute_chunk<T, RULE, 1, CONS>(k, G, gT, NCc, lds, L, C, hand_out, crow, hrow, ct_base, lane63, lane,
-                                    cq, tq, tprev_w, H, Np, a, crec);
-  for (; k < NCc; ++k)
-    compute_chunk<T, RULE, 2, CONS>(k, G, gT, NCc, lds, L, C, hand_out, crow, hrow, ct_base, lane63, lane,
-                                    cq, tq, tprev_w, H, Np, a, crec);
+  // The first four chunks (groups 0..15, where lanes left of column 0 are masked).
+  for (; k < 4; k += 2) {
+    WF_CHUNK(0, k, cA, tA, cB, tB);
+    WF_CHUNK(0, k + 1, cB, tB, cA, tA);
+  }
+  // Interior, two chunks per pass so the register sets alternate without copies.
+  for (; 4 * k + 12 <= gT; k += 2) {
+    WF_CHUNK(1, k, cA, tA, cB, tB);
+    WF_CHUNK(1, k + 1, cB, tB, cA, tA);
+  }
+  for (; k < NCc; ++k) {
+    if ((k & 1) == 0) WF_CHUNK(2, k, cA, tA, cB, tB);
+    else WF_CHUNK(2, k, cB, tB, cA, tA);
+  }
+#undef WF_CHUNK
   CBAR();
   if (lane == 0) st_ctl(&L.progress, (uint32_t)(4 * G));
 }
@@ -565,6 +605,18 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
   }
   const uint32_t slot0 = (uint32_t)(uintptr_t)L8(L.cring);
   const int NC = B.NC;
+  // Chunks [0, k_clean) of a full strip have every lane's quads inside the grid: they
+  // are issued from precomputed byte offsets (chunk k adds 64k) with no per-lane checks
+  // and need no fix-up.  The largest offset of chunk k is that of row 63, quad 3.
+  int k_clean = 0;
+  if (B.row0 + 63 <= B.m - 1) {
+    const int64_t max_rel = 63 * g.ld_cost + 12 - 63;
+    const int64_t room = span - 4 - max_rel;
+    if (room >= 0) k_clean = (int)(room / 16 + 1 < NC ? room / 16 + 1 : NC);
+  }
+  uint32_t voff0[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) voff0[i] = (uint32_t)(ln.rel[i] * 4);  // used only for clean chunks
   int issued = 0, committed = 0;
   Watch t_idle;
   uint32_t polls = 0;
@@ -572,20 +624,32 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
     // Issue every chunk whose slot the compute wave has released: slot k % C_SLOTS
     // last held chunk k - C_SLOTS, read completely once progress >= 16 (k - C_SLOTS + 1).
     while (issued < NC && (int)ld_ctl(&L.progress) >= 16 * (issued - C_SLOTS + 1)) {
-      const uint32_t base = slot0 + (uint32_t)((issued % C_SLOTS) * SLOT);
+      const uint32_t base = __builtin_amdgcn_readfirstlane(slot0 + (uint32_t)((issued % C_SLOTS) * SLOT));
+      if (issued < k_clean) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t e = ln.rel[i] + 16 * issued;  // element offset from the strip base
-        // Quads not wholly inside [strip base, end of grid) are not loaded at all (an
-        // out-of-range offset): rows past the end of a ragged strip and the grid's tail.
-        const uint32_t voff = (e < 0 || e + 4 > span) ? 0xFFFFFFFFu : (uint32_t)(e * 4);
-        dma_quad16(rsrc, voff, __builtin_amdgcn_readfirstlane(base + 1024u * i));
+        for (int i = 0; i < 4; ++i) dma_quad16(rsrc, voff0[i] + 64u * (uint32_t)issued, base + 1024u * i);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t e = ln.rel[i] + 16 * issued;  // element offset from the strip base
+          // Quads not wholly inside [strip base, end of grid) are not loaded at all (an
+          // out-of-range offset): rows past the end of a ragged strip and the grid's tail.
+          const uint32_t voff = (e < 0 || e + 4 > span) ? 0xFFFFFFFFu : (uint32_t)(e * 4);
+          dma_quad16(rsrc, voff, base + 1024u * i);
+        }
       }
       ++issued;
     }
     if (committed < issued) {
       const int k = committed;
       wait_dma(issued - committed - 1);
+      if (k < k_clean) {
+        CBAR();
+        if (lane == 0) st_ctl(&L.c_ready, (uint32_t)(k + 1));
+        ++committed;
+        t_idle.reset();
+        continue;
+      }
       // Quads that straddle the end of the grid and hold columns of a real row.
       bool fix[4];
       bool any = false;
@@ -631,6 +695,21 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
 
 // Store chunk k of H (64 rows x 16 positions) from the H ring: lane L covers
 // row 16i + L%16, positions 16k + 4(L/16) .. +3 (contiguous LDS reads).
+// Interior chunks of full-mode strips take the fast path: every quad lies inside the
+// grid and no edge output is due, so each lane stores its four quads unconditionally
+// (`qbase[i]` points at the lane's quad of chunk 0, column 4(L/16) - row).
+__device__ __forceinline__ bool store_fast(const GridDesc& g, const BandGeom& B, int k) {
+  return g.mode == 0 && k >= 4 && 16 * (int64_t)k + 16 < B.n && B.row0 + 64 < B.m;
+}
+
+__device__ __forceinline__ void store_chunk_fast(WaveLds& L, int k, int lane, glb_u32* const (&qbase)[4]) {
+  u4 v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = lds_ld4(L8(L.hring) + (k % H_SLOTS) * SLOT + 1024 * i + 16 * lane);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) *(glb_u4a4*)(qbase[i] + 16 * k) = v[i];
+}
+
 __device__ __forceinline__ void store_chunk(const GridDesc& g, const BandGeom& B, WaveLds& L, int k, int lane) {
   u4 v[4];
 #pragma unroll
@@ -665,6 +744,12 @@ __device__ __forceinline__ void store_chunk(const GridDesc& g, const BandGeom& B
   }
 }
 
+// Edges mode has nothing to store for an interior chunk of a strip that does not hold
+// the last row.
+__device__ __forceinline__ bool store_none(const GridDesc& g, const BandGeom& B, int k) {
+  return g.mode != 0 && 16 * (int64_t)k + 16 < B.n && B.row0 + 64 < B.m;
+}
+
 // One storer serves compute waves 2s and 2s+1.
 template <typename T, int W>
 __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds* lds, int s, int lane,
@@ -674,6 +759,7 @@ __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds
   BandGeom B[PER];
   bool active[PER];
   int ks[PER], tr[PER];
+  glb_u32* qbase[PER][4];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int w = PER * s + j;
@@ -681,6 +767,12 @@ __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds
     active[j] = w < W && B[j].row0 < B[j].m;
     ks[j] = 0;
     tr[j] = 60;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rho = 16 * i + (lane & 15);
+      // Only dereferenced on the fast path, where the strip is full and the quad interior.
+      qbase[j][i] = G32((uint32_t*)g.out) + (B[j].row0 + rho) * g.ld_out + 4 * (lane >> 4) - rho;
+    }
   }
   // Handoff-row re-arming: only the storer of compute wave 0, only below band 0.
   const bool rearm_hand = s == 0 && band > 0;
@@ -700,7 +792,8 @@ __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds
       CBAR();
       const int lim = 16 * (ks[j] + 1) < B[j].T_END ? 16 * (ks[j] + 1) : B[j].T_END;
       if (ks[j] < B[j].NC && prog >= lim) {
-        store_chunk(g, B[j], L, ks[j], lane);
+        if (store_fast(g, B[j], ks[j])) store_chunk_fast(L, ks[j], lane, qbase[j]);
+        else if (!store_none(g, B[j], ks[j])) store_chunk(g, B[j], L, ks[j], lane);
         ++ks[j];
         __builtin_amdgcn_s_waitcnt(0xc07f);  // the ring reads are done before the slot is released
         CBAR();

@@ -129,14 +129,16 @@ static wf_status ensure_buf(T** p, size_t* cap, size_t need) {
 }
 
 // --------------------------------------------------------------- checking
-static const int64_t MAX_N = (int64_t)1 << 28;  // positions are 32-bit inside the kernel
+// Positions are 32-bit inside the kernel, and a 64-row strip must span less than 4 GiB
+// (the loaders address it with 32-bit byte offsets): 64 rows of 2^23 fp32 are 2 GiB.
+static const int64_t MAX_N = (int64_t)1 << 23;
 
 wf_status wfh::check_problem(const wf_problem* p, int64_t idx) {
   char where[64] = "";
   if (idx >= 0) snprintf(where, sizeof where, "problem %lld: ", (long long)idx);
   if (!p) return fail(WF_EINVAL, std::string(where) + "NULL problem");
   if (p->m < 0 || p->n < 0) return fail(WF_EINVAL, std::string(where) + "m and n must be >= 0");
-  if (p->n > MAX_N) return fail(WF_EUNSUPPORTED, std::string(where) + "n above 2^28 is not supported");
+  if (p->n > MAX_N) return fail(WF_EUNSUPPORTED, std::string(where) + "n above 2^23 is not supported");
   if (p->dtype != WF_F32 && p->dtype != WF_I32) return fail(WF_EINVAL, std::string(where) + "unknown dtype");
   if (p->rule != WF_RULE_MIN && p->rule != WF_RULE_MAX) return fail(WF_EINVAL, std::string(where) + "unknown rule");
   if (p->mode != WF_MODE_FULL && p->mode != WF_MODE_EDGES) return fail(WF_EINVAL, std::string(where) + "unknown mode");
@@ -144,6 +146,7 @@ wf_status wfh::check_problem(const wf_problem* p, int64_t idx) {
   if (p->m == 0 || p->n == 0) return WF_OK;
   if (!p->cost) return fail(WF_EINVAL, std::string(where) + "cost is NULL");
   if (p->ld_cost < p->n) return fail(WF_EINVAL, std::string(where) + "ld_cost < n");
+  if (p->ld_cost > MAX_N) return fail(WF_EUNSUPPORTED, std::string(where) + "ld_cost above 2^23 is not supported");
   if (p->mode == WF_MODE_FULL) {
     if (!p->out) return fail(WF_EINVAL, std::string(where) + "out is NULL in FULL mode");
     if (p->ld_out < p->n) return fail(WF_EINVAL, std::string(where) + "ld_out < n");

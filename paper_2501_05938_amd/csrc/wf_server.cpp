@@ -171,6 +171,8 @@ struct LaunchSlot {
   GridDesc* h_grids = nullptr;  // pinned staging, valid until `done` fires
   Item* h_items = nullptr;
   size_t h_grids_cap = 0, h_items_cap = 0;
+  unsigned char* h_stage = nullptr;  // pinned staging of host inputs, valid until `done` fires
+  size_t h_stage_cap = 0;
   uint32_t* host_err = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
@@ -180,10 +182,10 @@ struct LaunchSlot {
 template <class T>
 wf_status grow_dev(T** p, size_t* cap, size_t need) {
   if (*cap >= need) return WF_OK;
+  const size_t c = std::max<size_t>(std::max<size_t>(need, 256), 2 * *cap);
   if (*p) hipFree(*p);
   *p = nullptr;
   *cap = 0;
-  const size_t c = std::max<size_t>(need, 256);
   if (hipMalloc(p, c * sizeof(T)) != hipSuccess) return fail(WF_ENOMEM, "cannot allocate a launch table");
   *cap = c;
   return WF_OK;
@@ -192,10 +194,10 @@ wf_status grow_dev(T** p, size_t* cap, size_t need) {
 template <class T>
 wf_status grow_host(T** p, size_t* cap, size_t need) {
   if (*cap >= need) return WF_OK;
+  const size_t c = std::max<size_t>(std::max<size_t>(need, 256), 2 * *cap);
   if (*p) hipHostFree(*p);
   *p = nullptr;
   *cap = 0;
-  const size_t c = std::max<size_t>(need, 256);
   if (hipHostMalloc((void**)p, c * sizeof(T), hipHostMallocDefault) != hipSuccess)
     return fail(WF_ENOMEM, "cannot allocate pinned staging");
   *cap = c;
@@ -280,12 +282,26 @@ void wf_server::admit(double t) {
 
 wf_status wf_server::enqueue(LaunchSlot& L, std::vector<Req*>& batch, int W, int dtype, int rule) {
   hipStream_t s = L.stream;
-  // Inputs and handoff rows.
+  // Host inputs go through the slot's pinned staging buffer: a copy from pageable memory
+  // is staged synchronously by the runtime in the calling thread, which would make the
+  // server thread block on the device (and on other threads' device-wide waits).
+  size_t stage = 0;
+  for (Req* q : batch)
+    if (q->r.input_kind == WF_INPUT_HOST) stage += (size_t)q->r.m * (size_t)q->r.n * 4;
+  if (stage) {
+    wf_status st = grow_host(&L.h_stage, &L.h_stage_cap, stage);
+    if (st != WF_OK) return st;
+  }
   const uint32_t sent = sentinel_of(dtype);
+  size_t at = 0;
   for (Req* q : batch) {
-    if (q->r.input_kind == WF_INPUT_HOST)
-      WF_HIP(hipMemcpy2DAsync((void*)q->in, (size_t)q->ld_in * 4, q->r.input, (size_t)q->r.ld_input * 4,
-                              (size_t)q->r.n * 4, (size_t)q->r.m, hipMemcpyHostToDevice, s));
+    if (q->r.input_kind == WF_INPUT_HOST) {
+      const size_t row = (size_t)q->r.n * 4, bytes = row * (size_t)q->r.m;
+      for (int64_t i = 0; i < q->r.m; ++i)
+        std::memcpy(L.h_stage + at + (size_t)i * row, (const char*)q->r.input + (size_t)i * (size_t)q->r.ld_input * 4, row);
+      WF_HIP(hipMemcpyAsync((void*)q->in, L.h_stage + at, bytes, hipMemcpyHostToDevice, s));
+      at += bytes;
+    }
     if (q->hand_n) WF_HIP(launch_fill_u32(q->hand, sent, (int64_t)q->hand_n, s));
   }
   // Descriptors, largest grid first, and the grid-major work list.
@@ -460,7 +476,8 @@ extern "C" wf_status wf_submit(wf_server* s, const wf_request* r, uint64_t* tick
     return fail(WF_EINVAL, "unknown input kind");
   const bool empty = r->m == 0 || r->n == 0;
   if (!empty && (!r->input || r->ld_input < r->n)) return fail(WF_EINVAL, "input is NULL or ld_input < n");
-  if (r->n > ((int64_t)1 << 28)) return fail(WF_EUNSUPPORTED, "n above 2^28 is not supported");
+  if (r->n > ((int64_t)1 << 23) || (r->input_kind == WF_INPUT_DEVICE && r->ld_input > ((int64_t)1 << 23)))
+    return fail(WF_EUNSUPPORTED, "n or ld_input above 2^23 is not supported");
   Req q;
   q.r = *r;
   q.t_submit = now_s();
@@ -554,6 +571,7 @@ extern "C" wf_status wf_server_destroy(wf_server* s) {
     if (L.d_items) hipFree(L.d_items);
     if (L.h_grids) hipHostFree(L.h_grids);
     if (L.h_items) hipHostFree(L.h_items);
+    if (L.h_stage) hipHostFree(L.h_stage);
     if (L.host_err) hipHostFree(L.host_err);
     if (L.done) hipEventDestroy(L.done);
   }

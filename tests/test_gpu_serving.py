@@ -3,6 +3,9 @@
 Each served result must be bit-identical to the same grid swept alone with
 wf_solve (and, for a few, to the CPU oracle): admission, batching with other
 requests and overlap with other launches must not change a single bit.
+
+While the server has launches in flight the tests wait on torch's own stream
+only (never a device-wide synchronize), as a serving client would.
 """
 import time
 
@@ -37,7 +40,12 @@ def _wait_all(srv, tickets, timeout_s=60.0):
     return done
 
 
+def _sync():
+    torch.cuda.current_stream().synchronize()
+
+
 def _bits(t):
+    _sync()
     a = t.cpu().numpy()
     return a.view(np.uint32) if a.dtype == np.float32 else a
 
@@ -61,14 +69,11 @@ def test_mix_equals_alone():
             c = wfgen.cells(seed, m, n, dt)
             x = c if host else torch.from_numpy(c).to(DEV)
             inputs.append(c)
-            tickets.append(srv.submit(x, rule=rule, mode=mode))
-            # keep device inputs alive: the server holds a reference until release
-        torch.cuda.synchronize()
+            tickets.append(srv.submit(x, rule=rule, mode=mode))  # the binding keeps x alive
         res = _wait_all(srv, tickets)
         for (m, n, dt, rule, mode, host, seed), c, t in zip(specs, inputs, tickets):
             r = res[t]
             alone = wf.solve(torch.from_numpy(c).to(DEV), rule=rule)
-            torch.cuda.synchronize()
             exp = _bits(alone)
             if mode == "full":
                 assert np.array_equal(_bits(r["out"]), exp), (m, n, dt, rule, mode)
@@ -78,7 +83,7 @@ def test_mix_equals_alone():
             assert r["t_submit"] <= r["t_admit"] <= r["t_launch"] <= r["t_done"]
             srv.release(t)
         assert srv.memory()[0] == 0
-    wf.check()
+    _sync()
 
 
 def test_served_result_matches_oracle():
@@ -107,8 +112,9 @@ def test_budget_limits_admission():
                 r = srv.poll(t)
                 if r is not None:
                     exp = wf.solve(cs[tickets.index(t)])
-                    torch.cuda.synchronize()
-                    assert torch.equal(r["out"], exp)
+                    same = torch.equal(r["out"], exp)
+                    _sync()
+                    assert same
                     srv.release(t)  # frees memory so later requests are admitted
                     pending.discard(t)
             assert time.time() - t0 < 60, "admission stalled"
