@@ -102,7 +102,7 @@ typedef struct wf_problem {
 } wf_problem;
 
 typedef struct wf_tuning {
-  int32_t waves_per_wg;    /* compute waves per workgroup: 1, 2 or 4 (0 = automatic) */
+  int32_t waves_per_wg;    /* compute waves per workgroup: 1, 2 or 3 (0 = automatic) */
   int32_t max_wgs;         /* persistent workgroups per launch (0 = automatic) */
   int32_t order;           /* batched work order: 0 = automatic, 1 = grid-major, 2 = interleaved by band */
   int32_t use_graph;       /* batched: 1 = capture and replay a hipGraph, 0 = plain launch,
@@ -128,7 +128,7 @@ wf_status wf_solve(wf_ctx* ctx, const wf_problem* p, void* stream);
  * Autotuning: when `t` is NULL or leaves both waves_per_wg and order at 0 (and
  * use_graph is not -1), the first call for a batch shape (count, sizes, dtype,
  * rule, mode) runs the batch once per candidate configuration (waves per
- * workgroup 1, 2, 4 x grid-major / interleaved order), synchronously, timed
+ * workgroup 1, 2, 3 x grid-major / interleaved order), synchronously, timed
  * on `stream`, and keeps the fastest in the context's tuning table; later
  * calls with that shape use it.  Every trial writes the full, correct result.
  * With use_graph = 1 the chosen launch is captured in a hipGraph and replayed

@@ -67,8 +67,8 @@ struct alignas(16) WaveLds {
   uint32_t tring[RING_T];
   uint32_t c_ready;   // chunks of c committed to cring (IO -> compute)
   uint32_t h_done;    // positions of H stored out of hring (IO -> compute)
-  uint32_t progress;  // (signed) positions computed; T positions < progress + 64 validated (compute -> IO)
-  uint32_t t_reset;   // T positions below this are re-armed (IO -> producer); slots < t_reset + RING_T writable
+  uint32_t progress;  // (signed) position of the chunk being computed: earlier chunks are done (compute -> IO)
+  uint32_t t_reset;   // T positions below this are re-armed (by this wave; -> producer); slots < t_reset + RING_T writable
   uint32_t abort;     // workgroup abort flag (only lds[0].abort is used)
   uint32_t t_fed;     // wave 0: T positions copied into the ring by the feeder (feeder -> storer)
   uint32_t pad[2];
@@ -281,14 +281,13 @@ __device__ __forceinline__ void read_chunk(int kn, int gT, const lds_u8* crow, c
 // a check that passes on values read earlier also passes on current ones; one that
 // fails falls back to waiting on fresh reads.
 struct CtlSnap {
-  uint32_t c_ready, h_done, t_reset, cons_t_reset;
+  uint32_t c_ready, h_done, cons_t_reset;
 };
 
 template <int CONS>
 __device__ __forceinline__ void snap_ctl(WaveLds& L, WaveLds* C, CtlSnap& s) {
   s.c_ready = ld_ctl(&L.c_ready);
   s.h_done = ld_ctl(&L.h_done);
-  s.t_reset = ld_ctl(&L.t_reset);
   s.cons_t_reset = CONS == 1 ? ld_ctl(&C->t_reset) : 0u;
 }
 
@@ -325,16 +324,13 @@ __device__ __forceinline__ void compute_chunk(
     const int need_c = k + 2 < NCc ? k + 2 : NCc;
     const int need_h = pos + CHUNK - H_SLOTS * CHUNK;
     const int need_t = pos + CHUNK - RING_T;
-    const int need_own_t = pos + 2 * CHUNK + 64 - RING_T;
     auto ok = [&](const CtlSnap& v) {
-      return (int)v.c_ready >= need_c && (int)v.h_done >= need_h && (int)v.t_reset >= need_own_t &&
-             (CONS != 1 || (int)v.cons_t_reset >= need_t);
+      return (int)v.c_ready >= need_c && (int)v.h_done >= need_h && (CONS != 1 || (int)v.cons_t_reset >= need_t);
     };
     if (!ok(snap)) {
       const uint64_t c0 = a.trace ? __builtin_readcyclecounter() : 0;
       if (rec && lane == 0) {
         rec[3] = ((int)snap.c_ready < need_c ? 1u : 0u) | ((int)snap.h_done < need_h ? 2u : 0u) |
-                 ((int)snap.t_reset < need_own_t ? 4u : 0u) |
                  (CONS == 1 && (int)snap.cons_t_reset < need_t ? 8u : 0u);
       }
       wait_until<false>([&] { snap_ctl<CONS>(L, C, snap); return ok(snap); }, lds, a);
@@ -377,6 +373,16 @@ __device__ __forceinline__ void compute_chunk(
       __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the re-read quads are in registers
       if (a.trace && lane == 0) L.tr_t_wait += __builtin_readcyclecounter() - c0;
     }
+    // The chunk's quads are in registers: re-arm their slots for the next lap (lane q
+    // writes quad q) and let the producer reuse them.  LDS accesses of one wave complete
+    // in order, so the producer sees the sentinels before the new limit.
+    const int nq = KIND == 1 ? 4 : (gT - 4 * k < 4 ? gT - 4 * k : 4);
+    if (lane < nq) {
+      const u4 s4 = {SENT, SENT, SENT, SENT};
+      lds_st4(L8(L.tring) + (tpos + 4 * lane) * 4, s4);
+    }
+    CBAR();
+    if (lane == 0) st_ctl(&L.t_reset, (uint32_t)(pos + 64 + 4 * nq));
   }
   read_chunk<KIND == 1 ? 1 : 0>(k + 1, gT, crow, tr_base, cn, tn);
   lds_u8* hb = hrow + (k % H_SLOTS) * SLOT;
@@ -425,6 +431,10 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   if (a.trace && lane == 0) L.tr_first = __builtin_readcyclecounter();
   T Np = from_bits<T>(tprev.z);
   uint32_t tprev_w = tprev.w;
+  if (lane == 0) {
+    const u4 s4 = {Num<T>::SENT, Num<T>::SENT, Num<T>::SENT, Num<T>::SENT};
+    lds_st4(L8(L.tring) + 60 * 4, s4);
+  }
   // Inputs of the current chunk and of the next one, in two register sets used in turn.
   u4 cA[4], tA[4], cB[4], tB[4];
   wait_until<false>([&] { return ld_ctl(&L.c_ready) >= 1u; }, lds, a);
@@ -454,7 +464,11 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   }
 #undef WF_CHUNK
   CBAR();
-  if (lane == 0) st_ctl(&L.progress, (uint32_t)(4 * G));
+  if (lane == 0) {
+    st_ctl(&L.progress, (uint32_t)(4 * G));
+    // Every T position this walk reads has been consumed: release the producer's tail.
+    st_ctl(&L.t_reset, (uint32_t)(4 * G));
+  }
 }
 
 template <typename T, int RULE, int W>
@@ -750,15 +764,15 @@ __device__ __forceinline__ bool store_none(const GridDesc& g, const BandGeom& B,
   return g.mode != 0 && 16 * (int64_t)k + 16 < B.n && B.row0 + 64 < B.m;
 }
 
-// One storer serves compute waves 2s and 2s+1.
+// Storer s serves compute wave s.
 template <typename T, int W>
 __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds* lds, int s, int lane,
                                             const KArgs& a) {
   const uint32_t SENT = Num<T>::SENT;
-  constexpr int PER = 2;
+  constexpr int PER = 1;
   BandGeom B[PER];
   bool active[PER];
-  int ks[PER], tr[PER];
+  int ks[PER];
   glb_u32* qbase[PER][4];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
@@ -766,7 +780,6 @@ __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds
     B[j] = band_geom<W>(g, band, w < W ? w : 0);
     active[j] = w < W && B[j].row0 < B[j].m;
     ks[j] = 0;
-    tr[j] = 60;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int rho = 16 * i + (lane & 15);
@@ -788,36 +801,23 @@ __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds
     for (int j = 0; j < PER; ++j) {
       if (!active[j]) continue;
       WaveLds& L = lds[PER * s + j];
+      // Store every chunk the compute wave has finished (progress >= 16 (k+1), or the
+      // end of the walk), then release their H slots at once.
       const int prog = (int)ld_ctl(&L.progress);
       CBAR();
-      const int lim = 16 * (ks[j] + 1) < B[j].T_END ? 16 * (ks[j] + 1) : B[j].T_END;
-      if (ks[j] < B[j].NC && prog >= lim) {
+      const int k0 = ks[j];
+      while (ks[j] < B[j].NC && prog >= (16 * (ks[j] + 1) < B[j].T_END ? 16 * (ks[j] + 1) : B[j].T_END)) {
         if (store_fast(g, B[j], ks[j])) store_chunk_fast(L, ks[j], lane, qbase[j]);
         else if (!store_none(g, B[j], ks[j])) store_chunk(g, B[j], L, ks[j], lane);
         ++ks[j];
-        __builtin_amdgcn_s_waitcnt(0xc07f);  // the ring reads are done before the slot is released
+      }
+      if (ks[j] > k0) {
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // the ring reads are done before the slots are released
         CBAR();
         if (lane == 0) st_ctl(&L.h_done, (uint32_t)(16 * ks[j]));
         did = true;
       }
-      int target = prog + 64;
-      if (target > B[j].T_END) target = B[j].T_END;
-      if (target > tr[j]) {
-        const int nq = (target - tr[j]) / 4;
-        for (int base = 0; base < nq; base += 64) {
-          if (base + lane < nq) {
-            const int p = tr[j] + 4 * (base + lane);
-            u4 s4 = {SENT, SENT, SENT, SENT};
-            lds_st4(L8(L.tring) + (p & (RING_T - 1)) * 4, s4);
-          }
-        }
-        tr[j] = target;
-        __builtin_amdgcn_s_waitcnt(0xc07f);
-        CBAR();
-        if (lane == 0) st_ctl(&L.t_reset, (uint32_t)tr[j]);
-        did = true;
-      }
-      if (ks[j] < B[j].NC || tr[j] < B[j].T_END) done = false;
+      if (ks[j] < B[j].NC) done = false;
     }
     if (rearm_hand) {
       const int fed = (int)ld_ctl(&lds[0].t_fed);
@@ -905,7 +905,9 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
 }
 
 // ------------------------------------------------------------------ kernel
-constexpr int storers_for(int W) { return (W + 1) / 2; }
+// One storer per compute wave: at full speed a compute wave finishes a chunk about as
+// fast as one wave can issue that chunk's H stores while every strip is storing.
+constexpr int storers_for(int W) { return W; }
 constexpr int waves_for(int W) { return 2 * W + storers_for(W) + 1; }
 
 // Three waves per SIMD at most, so at most 168 VGPRs each.
@@ -994,7 +996,7 @@ hipError_t launch_w(int W, int nwg, const KArgs& args, hipStream_t stream) {
   switch (W) {
     case 1: return launch_t<T, RULE, 1>(nwg, args, stream);
     case 2: return launch_t<T, RULE, 2>(nwg, args, stream);
-    case 4: return launch_t<T, RULE, 4>(nwg, args, stream);
+    case 3: return launch_t<T, RULE, 3>(nwg, args, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -160,12 +160,14 @@ wf_status wfh::check_problem(const wf_problem* p, int64_t idx) {
 int wfh::choose_waves(int64_t m) {
   // Bands of 64*W rows.  Inside a workgroup the bottom-row handoff goes through
   // LDS; across workgroups it goes through memory, so tall grids want W = 4.
-  if (m >= 2048) return 4;
+  if (m >= 1536) return 3;
   if (m >= 512) return 2;
   return 1;
 }
 
-int wfh::wgs_per_cu(int W) { return W >= 4 ? 1 : (W == 2 ? 2 : 3); }
+// At most 12 waves per compute unit (3 per SIMD at this kernel's register use), and the
+// LDS rings of W compute waves per workgroup.
+int wfh::wgs_per_cu(int W) { return W >= 2 ? 1 : 3; }
 
 uint32_t wfh::sentinel_of(int dtype) { return dtype == WF_F32 ? SENT_F32 : SENT_I32; }
 
@@ -497,7 +499,7 @@ static wf_status autotune(wf_ctx* ctx, const wf_problem* ps, int64_t count, int 
   WF_HIP(hipEventCreate(&e1));
   float best = -1.f;
   int bw = 1, bo = 1;
-  static const int Ws[] = {1, 2, 4};
+  static const int Ws[] = {1, 2, 3};
   wf_status st = WF_OK;
   for (int W : Ws) {
     for (int order = 1; order <= 2 && st == WF_OK; ++order) {
@@ -544,8 +546,7 @@ extern "C" wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t
   if (t) tun = *t;
   for (int i = 0; i < 4; ++i)
     if (tun.reserved[i] != 0) return fail(WF_EINVAL, "wf_tuning.reserved must be 0");
-  if (tun.waves_per_wg != 0 && tun.waves_per_wg != 1 && tun.waves_per_wg != 2 && tun.waves_per_wg != 4)
-    return fail(WF_EINVAL, "waves_per_wg must be 0, 1, 2 or 4");
+  if (tun.waves_per_wg < 0 || tun.waves_per_wg > 3) return fail(WF_EINVAL, "waves_per_wg must be 0, 1, 2 or 3");
   if (tun.max_wgs < 0 || tun.order < 0 || tun.order > 2 || tun.use_graph < -1 || tun.use_graph > 1)
     return fail(WF_EINVAL, "bad tuning value");
   wf_status st = set_device(ctx);
