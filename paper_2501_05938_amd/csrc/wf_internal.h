@@ -50,9 +50,11 @@ constexpr int TRACE_WORDS = 8;
 // 0, CTRACE_EVERY, 2*CTRACE_EVERY, ...):
 //   [0] wall clock on reaching the chunk start   [1] wall clock when its wait ended
 //   [2] cycles spent so far waiting for top-boundary quads (needs KArgs::trace)
-//   [3] which conditions were not met on arrival: 1 c ring, 2 H ring, 4 own T ring,
-//       8 consumer's T ring
-constexpr int CTRACE_WORDS = 4;
+//   [3] which conditions were not met on arrival: 1 c ring, 2 H ring, 8 consumer's T ring
+//   [4] loader: wall clock when the chunk's loads were issued  [5] when they had landed
+//   [6] storer: wall clock when it began storing the chunk (or the last of a run of chunks
+//       stored together)  [7] when it released the chunk's H slot
+constexpr int CTRACE_WORDS = 8;
 constexpr int CTRACE_EVERY = 8;   // one record per this many chunks
 
 // Control-word indices.

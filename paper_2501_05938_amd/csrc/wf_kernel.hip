@@ -48,15 +48,17 @@ namespace {
 constexpr int CHUNK = 16;               // positions per IO chunk
 constexpr int SLOT = 64 * CHUNK * 4;    // bytes of one chunk slot (64 rows x 16 positions)
 constexpr int C_SLOTS = 6;              // chunk slots of the c ring
-constexpr int H_SLOTS = 3;              // chunk slots of the H ring
-constexpr int RING_T = 128;             // positions held by the T ring
+constexpr int H_SLOTS = 6;              // chunk slots of the H ring
+constexpr int RING_T = 256;             // positions held by the T ring
 // Inside a slot, the 16 bytes of row r, quad q (positions 4q..4q+3 of the chunk)
-// sit at (r/16)*1024 + q*256 + (r%16)*16: for one quad, 16 consecutive rows are
-// 256 contiguous bytes, so a wave's 16-byte accesses to one quad never share a
-// bank cycle, and a 64-lane LDS-DMA load (lane L -> byte 16L) fills one quad of
-// 16 rows in each of four 1024-byte blocks.
-constexpr int QUAD = 256;
-__device__ __forceinline__ int lane_off(int r) { return (r >> 4) * 1024 + (r & 15) * 16; }
+// sit at (r/16)*1024 + (r%16)*64 + q*16: a 1024-byte block holds 16 whole rows of
+// the chunk.  A 64-lane LDS-DMA load (lane L -> byte 16L) then fills one block with
+// lanes 4j..4j+3 reading one row's 64 contiguous bytes, so the global accesses of
+// four consecutive lanes coalesce; the storer reads the H ring the same way.  The
+// compute wave's per-row 16-byte accesses to one quad are 64 bytes apart (a 4-way
+// bank conflict on these few prefetch reads and stores).
+constexpr int QUAD = 16;
+__device__ __forceinline__ int lane_off(int r) { return (r >> 4) * 1024 + (r & 15) * 64; }
 
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u4a4 __attribute__((ext_vector_type(4), aligned(4)));
@@ -215,6 +217,13 @@ __device__ __forceinline__ bool wait_until(F&& cond, WaveLds* lds, const KArgs& 
       return false;
     }
   }
+}
+
+// Sampled per-chunk trace record of compute wave w (see CTRACE_WORDS), or null.
+typedef __attribute__((address_space(1))) uint64_t glb_u64;
+__device__ __forceinline__ glb_u64* chunk_rec(const KArgs& a, uint32_t item, int W, int w, int k) {
+  if (!a.ctrace || (k % CTRACE_EVERY) != 0) return nullptr;
+  return (glb_u64*)(void*)(a.ctrace + (((int64_t)item * W + w) * a.ctrace_nc + k / CTRACE_EVERY) * CTRACE_WORDS);
 }
 
 // ------------------------------------------------------------ compute wave
@@ -536,8 +545,8 @@ __device__ __forceinline__ BandGeom band_geom(const GridDesc& g, int band, int w
 // ------------------------------------------------------------- loader
 // Chunk k of c for the 64 rows of a strip goes straight from memory into c-ring
 // slot k % C_SLOTS with LDS-DMA loads (buffer_load_dwordx4 ... lds): load i
-// covers rows 16i .. 16i+15, lane L reading row 16i + L%16 at positions
-// 16k + 4(L/16) .. +3, i.e. columns col .. col+3 with col = 16k + 4(L/16) - row.
+// covers rows 16i .. 16i+15, lane L reading row 16i + L/4 at positions
+// 16k + 4(L%4) .. +3, i.e. columns col .. col+3 with col = 16k + 4(L%4) - row.
 // The hardware writes lane L's 16 bytes at M0 + 16L, which is the slot layout.
 //
 // Offsets are taken from a buffer descriptor based at the strip's first row
@@ -574,7 +583,7 @@ __device__ __forceinline__ void wait_dma(int younger) {
 static_assert(C_SLOTS <= 6, "wait_dma covers at most 5 younger chunks");
 
 struct LoaderLanes {
-  int64_t rel[4];    // element offset of (row, column 16k' + 4(L/16) - row) for k' = 0, from the strip base
+  int64_t rel[4];    // element offset of (row, column 16k' + 4(L%4) - row) for k' = 0, from the strip base
   int rho[4];        // row inside the strip (not clamped)
   bool real[4];      // the row exists
 };
@@ -599,7 +608,7 @@ __device__ __forceinline__ bool io_idle(WaveLds* lds, const KArgs& a, Watch& w, 
 
 template <int W>
 __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds* lds, int w, int lane,
-                                            const KArgs& a) {
+                                            const KArgs& a, uint32_t item) {
   const BandGeom B = band_geom<W>(g, band, w);
   if (B.row0 >= B.m) return;
   WaveLds& L = lds[w];
@@ -611,11 +620,11 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
   LoaderLanes ln;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int rho = 16 * i + (lane & 15);
+    const int rho = 16 * i + (lane >> 2);
     const int64_t rr = rho < last_rho ? rho : last_rho;
     ln.rho[i] = rho;
     ln.real[i] = rho <= last_rho;
-    ln.rel[i] = rr * g.ld_cost + 4 * (lane >> 4) - rho;
+    ln.rel[i] = rr * g.ld_cost + 4 * (lane & 3) - rho;
   }
   const uint32_t slot0 = (uint32_t)(uintptr_t)L8(L.cring);
   const int NC = B.NC;
@@ -639,6 +648,8 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
     // last held chunk k - C_SLOTS, read completely once progress >= 16 (k - C_SLOTS + 1).
     while (issued < NC && (int)ld_ctl(&L.progress) >= 16 * (issued - C_SLOTS + 1)) {
       const uint32_t base = __builtin_amdgcn_readfirstlane(slot0 + (uint32_t)((issued % C_SLOTS) * SLOT));
+      if (glb_u64* r = chunk_rec(a, item, W, w, issued))
+        if (lane == 0) r[4] = wall_clock64();
       if (issued < k_clean) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) dma_quad16(rsrc, voff0[i] + 64u * (uint32_t)issued, base + 1024u * i);
@@ -657,6 +668,8 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
     if (committed < issued) {
       const int k = committed;
       wait_dma(issued - committed - 1);
+      if (glb_u64* r = chunk_rec(a, item, W, w, k))
+        if (lane == 0) r[5] = wall_clock64();
       if (k < k_clean) {
         CBAR();
         if (lane == 0) st_ctl(&L.c_ready, (uint32_t)(k + 1));
@@ -669,7 +682,7 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
       bool any = false;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int64_t col = 16 * k + 4 * (lane >> 4) - ln.rho[i];
+        const int64_t col = 16 * k + 4 * (lane & 3) - ln.rho[i];
         const int64_t e = ln.rel[i] + 16 * k;
         fix[i] = ln.real[i] && e + 4 > span && col <= B.n - 1 && col + 3 >= 0;
         any |= fix[i];
@@ -680,7 +693,7 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           if (!fix[i]) continue;
-          const int64_t col = 16 * k + 4 * (lane >> 4) - ln.rho[i];
+          const int64_t col = 16 * k + 4 * (lane & 3) - ln.rho[i];
           u4 v;
 #pragma unroll
           for (int e = 0; e < 4; ++e)
@@ -708,20 +721,35 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
 }
 
 // Store chunk k of H (64 rows x 16 positions) from the H ring: lane L covers
-// row 16i + L%16, positions 16k + 4(L/16) .. +3 (contiguous LDS reads).
-// Interior chunks of full-mode strips take the fast path: every quad lies inside the
-// grid and no edge output is due, so each lane stores its four quads unconditionally
-// (`qbase[i]` points at the lane's quad of chunk 0, column 4(L/16) - row).
-__device__ __forceinline__ bool store_fast(const GridDesc& g, const BandGeom& B, int k) {
-  return g.mode == 0 && k >= 4 && 16 * (int64_t)k + 16 < B.n && B.row0 + 64 < B.m;
+// row 16i + L/4, positions 16k + 4(L%4) .. +3 (contiguous LDS reads, and four
+// consecutive lanes store one row's 64 contiguous bytes).
+// Interior chunks (every quad inside the columns, none holding column n-1) take the
+// fast path: full strips store their four quads unconditionally (`qbase[i]` points at
+// the lane's quad of chunk 0, column 4(L%4) - row); the strip holding the last row
+// skips the rows past it and copies that row's quads to last_row as well.
+__device__ __forceinline__ bool store_interior(const BandGeom& B, int k) {
+  return k >= 4 && 16 * (int64_t)k + 16 < B.n;
 }
 
-__device__ __forceinline__ void store_chunk_fast(WaveLds& L, int k, int lane, glb_u32* const (&qbase)[4]) {
+template <bool LAST_STRIP>
+__device__ __forceinline__ void store_chunk_fast(const GridDesc& g, const BandGeom& B, WaveLds& L, int k, int lane,
+                                                 glb_u32* const (&qbase)[4]) {
   u4 v[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) v[i] = lds_ld4(L8(L.hring) + (k % H_SLOTS) * SLOT + 1024 * i + 16 * lane);
+  const bool full = g.mode == 0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) *(glb_u4a4*)(qbase[i] + 16 * k) = v[i];
+  for (int i = 0; i < 4; ++i) {
+    if (!LAST_STRIP) {
+      if (full) *(glb_u4a4*)(qbase[i] + 16 * k) = v[i];
+    } else {
+      const int rho = 16 * i + (lane >> 2);
+      const int64_t row = B.row0 + rho;
+      if (row < B.m && full) *(glb_u4a4*)(qbase[i] + 16 * k) = v[i];
+      if (row == B.m - 1 && g.last_row)
+        *(glb_u4a4*)(G32((uint32_t*)g.last_row) + 16 * (int64_t)k + 4 * (lane & 3) - rho) = v[i];
+    }
+  }
 }
 
 __device__ __forceinline__ void store_chunk(const GridDesc& g, const BandGeom& B, WaveLds& L, int k, int lane) {
@@ -731,9 +759,9 @@ __device__ __forceinline__ void store_chunk(const GridDesc& g, const BandGeom& B
   const bool full = g.mode == 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int rho = 16 * i + (lane & 15);
+    const int rho = 16 * i + (lane >> 2);
     const int64_t row = B.row0 + rho;
-    const int64_t col = 16 * k + 4 * (lane >> 4) - rho;
+    const int64_t col = 16 * k + 4 * (lane & 3) - rho;
     if (row >= B.m || col > B.n - 1 || col + 3 < 0) continue;
     if (full) {
       glb_u32* op = G32((uint32_t*)g.out + row * g.ld_out);
@@ -758,16 +786,10 @@ __device__ __forceinline__ void store_chunk(const GridDesc& g, const BandGeom& B
   }
 }
 
-// Edges mode has nothing to store for an interior chunk of a strip that does not hold
-// the last row.
-__device__ __forceinline__ bool store_none(const GridDesc& g, const BandGeom& B, int k) {
-  return g.mode != 0 && 16 * (int64_t)k + 16 < B.n && B.row0 + 64 < B.m;
-}
-
 // Storer s serves compute wave s.
 template <typename T, int W>
 __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds* lds, int s, int lane,
-                                            const KArgs& a) {
+                                            const KArgs& a, uint32_t item) {
   const uint32_t SENT = Num<T>::SENT;
   constexpr int PER = 1;
   BandGeom B[PER];
@@ -782,9 +804,9 @@ __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds
     ks[j] = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int rho = 16 * i + (lane & 15);
+      const int rho = 16 * i + (lane >> 2);
       // Only dereferenced on the fast path, where the strip is full and the quad interior.
-      qbase[j][i] = G32((uint32_t*)g.out) + (B[j].row0 + rho) * g.ld_out + 4 * (lane >> 4) - rho;
+      qbase[j][i] = G32((uint32_t*)g.out) + (B[j].row0 + rho) * g.ld_out + 4 * (lane & 3) - rho;
     }
   }
   // Handoff-row re-arming: only the storer of compute wave 0, only below band 0.
@@ -807,14 +829,22 @@ __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds
       CBAR();
       const int k0 = ks[j];
       while (ks[j] < B[j].NC && prog >= (16 * (ks[j] + 1) < B[j].T_END ? 16 * (ks[j] + 1) : B[j].T_END)) {
-        if (store_fast(g, B[j], ks[j])) store_chunk_fast(L, ks[j], lane, qbase[j]);
-        else if (!store_none(g, B[j], ks[j])) store_chunk(g, B[j], L, ks[j], lane);
+        if (glb_u64* r = chunk_rec(a, item, W, PER * s + j, ks[j]))
+          if (lane == 0) r[6] = wall_clock64();
+        if (!store_interior(B[j], ks[j])) store_chunk(g, B[j], L, ks[j], lane);
+        else if (B[j].row0 + 64 < B[j].m) store_chunk_fast<false>(g, B[j], L, ks[j], lane, qbase[j]);
+        else store_chunk_fast<true>(g, B[j], L, ks[j], lane, qbase[j]);
         ++ks[j];
       }
       if (ks[j] > k0) {
         __builtin_amdgcn_s_waitcnt(0xc07f);  // the ring reads are done before the slots are released
         CBAR();
         if (lane == 0) st_ctl(&L.h_done, (uint32_t)(16 * ks[j]));
+        if (a.ctrace && lane == 0) {
+          const uint64_t now = wall_clock64();
+          for (int kk = k0; kk < ks[j]; ++kk)
+            if (glb_u64* r = chunk_rec(a, item, W, PER * s + j, kk)) r[7] = now;
+        }
         did = true;
       }
       if (ks[j] < B[j].NC) done = false;
@@ -961,8 +991,8 @@ void wf_sweep_kernel(KArgs a) {
       uint64_t* crec = a.ctrace ? a.ctrace + ((int64_t)t * W + wave) * a.ctrace_nc * CTRACE_WORDS : nullptr;
       compute_band<T, RULE, W>(gd, band, lds, wave, lane, a, crec);
     }
-    else if (wave < 2 * W) loader_band<W>(gd, band, lds, wave - W, lane, a);
-    else if (wave < 2 * W + storers_for(W)) storer_band<T, W>(gd, band, lds, wave - 2 * W, lane, a);
+    else if (wave < 2 * W) loader_band<W>(gd, band, lds, wave - W, lane, a, t);
+    else if (wave < 2 * W + storers_for(W)) storer_band<T, W>(gd, band, lds, wave - 2 * W, lane, a, t);
     else feeder_band<T, RULE, W>(gd, band, lds, lane, a);
     __syncthreads();
     if (a.trace && wave < W && lane == 0) {
