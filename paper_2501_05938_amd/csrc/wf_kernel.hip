@@ -47,8 +47,8 @@ namespace {
 
 constexpr int CHUNK = 16;               // positions per IO chunk
 constexpr int SLOT = 64 * CHUNK * 4;    // bytes of one chunk slot (64 rows x 16 positions)
-constexpr int C_SLOTS = 6;              // chunk slots of the c ring
-constexpr int H_SLOTS = 6;              // chunk slots of the H ring
+constexpr int C_SLOTS = 8;              // chunk slots of the c ring
+constexpr int H_SLOTS = 4;              // chunk slots of the H ring
 constexpr int RING_T = 256;             // positions held by the T ring
 // Inside a slot, the 16 bytes of row r, quad q (positions 4q..4q+3 of the chunk)
 // sit at (r/16)*1024 + (r%16)*64 + q*16: a 1024-byte block holds 16 whole rows of
@@ -577,10 +577,12 @@ __device__ __forceinline__ void wait_dma(int younger) {
     case 2: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
     case 3: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
     case 4: asm volatile("s_waitcnt vmcnt(16)" ::: "memory"); break;
-    default: asm volatile("s_waitcnt vmcnt(20)" ::: "memory"); break;
+    case 5: asm volatile("s_waitcnt vmcnt(20)" ::: "memory"); break;
+    case 6: asm volatile("s_waitcnt vmcnt(24)" ::: "memory"); break;
+    default: asm volatile("s_waitcnt vmcnt(28)" ::: "memory"); break;
   }
 }
-static_assert(C_SLOTS <= 6, "wait_dma covers at most 5 younger chunks");
+static_assert(C_SLOTS <= 8, "wait_dma covers at most 7 younger chunks");
 
 struct LoaderLanes {
   int64_t rel[4];    // element offset of (row, column 16k' + 4(L%4) - row) for k' = 0, from the strip base
@@ -857,7 +859,9 @@ __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds
           if (base + lane < nq) {
             const int p = hr + 4 * (base + lane);
             u4 s4 = {SENT, SENT, SENT, SENT};
-            __builtin_amdgcn_raw_buffer_store_b128(s4, hand_in, p * 4, 0, 0);
+            // Device-coherent like every other access to the handoff rows: a plain store
+            // could linger in this XCD's L2 and reach memory after the next launch's data.
+            __builtin_amdgcn_raw_buffer_store_b128(s4, hand_in, p * 4, 0, CPOL_SC1);
           }
         }
         hr = fed;

@@ -158,10 +158,11 @@ wf_status wfh::check_problem(const wf_problem* p, int64_t idx) {
 
 // ------------------------------------------------------------ configuration
 int wfh::choose_waves(int64_t m) {
-  // Bands of 64*W rows.  Inside a workgroup the bottom-row handoff goes through
-  // LDS; across workgroups it goes through memory, so tall grids want W = 4.
-  if (m >= 1536) return 3;
-  if (m >= 512) return 2;
+  // Bands of 64*W rows.  A workgroup's W strips share one compute unit's memory
+  // pipeline (each strip has its own loader and storer), and that sharing costs more
+  // than the LDS handoff between them saves: one strip per workgroup, spread over the
+  // compute units, is fastest for a single grid.
+  (void)m;
   return 1;
 }
 
