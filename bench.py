@@ -11,7 +11,9 @@ the timed region only reads and writes HBM.
 Prints ONE JSON line.  Besides the contract fields it carries
   roofline:     the sweep kernel against the 8 TB/s HBM peak (algorithmic bytes:
                 4 B read + 4 B written per cell), per-launch time from HIP events
-                recorded on the launch stream;
+                recorded on the launch stream; `traffic` is the HBM bytes per launch
+                from the committed FETCH_SIZE / WRITE_SIZE summary when it was taken
+                on the current kernel sources (null otherwise);
   cpu_baseline: the CPU oracle (fp64 row-major loop, one thread) on the same
                 workload;
   batched:      4096 grids, m and n log-uniform in [64, 2048], one persistent
@@ -32,6 +34,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "sweep16384_memory_counters.md")
+KERNEL_SOURCES = ("paper_2501_05938_amd/csrc/wf_kernel.hip", "paper_2501_05938_amd/csrc/wf_internal.h")
 M = N = 16384
 SEED = 2
 
@@ -69,6 +73,25 @@ def time_events(torch, fn, steps, stream):
         ends[i].record(stream)
     torch.cuda.synchronize()
     return [s.elapsed_time(e) for s, e in zip(starts, ends)]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary, or None
+    when the kernel sources have changed since those counters were taken."""
+    import hashlib
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:"):
+            return float(line.split(":")[1])
+    return None
 
 
 def cpu_baseline(seconds: float):
@@ -298,7 +321,7 @@ def main():
         "config": {"workload": "single 16384x16384 grid, fp32, min rule, default boundary, full output",
                    "m": M, "n": N, "seed": SEED, "rule": "min", "mode": "full"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel_ms": kernel_ms, "kernel_ms_min": min(per),
                      "bytes_per_launch": alg_bytes, "bytes_per_cell": 8},
     }
