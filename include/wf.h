@@ -102,7 +102,7 @@ typedef struct wf_problem {
 } wf_problem;
 
 typedef struct wf_tuning {
-  int32_t waves_per_wg;    /* compute waves per workgroup: 1, 2 or 3 (0 = automatic) */
+  int32_t waves_per_wg;    /* compute waves per workgroup: 1 or 2 (0 = automatic) */
   int32_t max_wgs;         /* persistent workgroups per launch (0 = automatic) */
   int32_t order;           /* batched work order: 0 = automatic, 1 = grid-major, 2 = interleaved by band */
   int32_t use_graph;       /* batched: 1 = capture and replay a hipGraph, 0 = plain launch,

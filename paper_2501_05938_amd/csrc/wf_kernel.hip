@@ -48,7 +48,7 @@ namespace {
 constexpr int CHUNK = 16;               // positions per IO chunk
 constexpr int SLOT = 64 * CHUNK * 4;    // bytes of one chunk slot (64 rows x 16 positions)
 constexpr int C_SLOTS = 8;              // chunk slots of the c ring
-constexpr int H_SLOTS = 4;              // chunk slots of the H ring
+constexpr int H_SLOTS = 8;              // chunk slots of the H ring (slack for the storer's jitter)
 constexpr int RING_T = 256;             // positions held by the T ring
 // Inside a slot, the 16 bytes of row r, quad q (positions 4q..4q+3 of the chunk)
 // sit at (r/16)*1024 + (r%16)*64 + q*16: a 1024-byte block holds 16 whole rows of
@@ -123,6 +123,15 @@ template <> struct Num<int32_t> {
 };
 
 // N for every lane: lane r receives lane r-1's `src`; lane 0 keeps `old`.
+// Shift acc one lane down within each row of 16 lanes (lane i takes lane i+1) and put
+// this lane's h where no source lane exists (lanes 15, 31, 47, 63).  After j calls,
+// lane 63-i holds the h of the (j-i)-th call.
+__device__ __forceinline__ void shift_in_lane63(u4& acc, const u4& h) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    acc[e] = (uint32_t)__builtin_amdgcn_update_dpp((int)h[e], (int)acc[e], 0x101, 0xf, 0xf, false);
+}
+
 template <typename T> __device__ __forceinline__ T dpp_shr1(T old, T src) {
   return from_bits<T>((uint32_t)__builtin_amdgcn_update_dpp((int)bits(old), (int)bits(src), 0x138, 0xf, 0xf, false));
 }
@@ -396,6 +405,10 @@ __device__ __forceinline__ void compute_chunk(
   read_chunk<KIND == 1 ? 1 : 0>(k + 1, gT, crow, tr_base, cn, tn);
   lds_u8* hb = hrow + (k % H_SLOTS) * SLOT;
   lds_u8* ct = ct_base + (pos & (RING_T - 1)) * 4;
+  // Bottom-row quads of the chunk for the next band, gathered into lanes 60..63 (lane 63
+  // holds the last group's quad, lane 62 the one before, ...) and stored once at the end
+  // of the chunk.
+  u4 hand4 = {0u, 0u, 0u, 0u};
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int g = 4 * k + q;
@@ -418,12 +431,18 @@ __device__ __forceinline__ void compute_chunk(
     }
     // H into the ring, bottom row to the consumer.  Positions < 60 are never read by a consumer.
     lds_st4(hb + QUAD * q, h4);
-    if (CONS != 0 && (KIND != 0 || g >= 15)) {
-      if (lane63) {
-        if (CONS == 1) lds_st4(ct + 16 * q, h4);
-        else __builtin_amdgcn_raw_buffer_store_b128(h4, hand_out, 16 * g, 0, CPOL_SC1);
-      }
+    if (CONS == 1 && (KIND != 0 || g >= 15)) {
+      if (lane63) lds_st4(ct + 16 * q, h4);
     }
+    if (CONS == 2) shift_in_lane63(hand4, h4);
+  }
+  if (CONS == 2) {
+    // Group of lane 60..63's quad; positions below 60 are never read by a consumer and
+    // stay at the sentinel.
+    const int nq = KIND == 2 ? (G - 4 * k < 4 ? G - 4 * k : 4) : 4;
+    const int g = 4 * k + nq - 1 - (63 - lane);
+    if (lane >= 60 && g >= 4 * k && (KIND != 0 || g >= 15))
+      __builtin_amdgcn_raw_buffer_store_b128(hand4, hand_out, 16 * g, 0, CPOL_SC1);
   }
 }
 
@@ -944,11 +963,19 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
 constexpr int storers_for(int W) { return W; }
 constexpr int waves_for(int W) { return 2 * W + storers_for(W) + 1; }
 
-// Three waves per SIMD at most, so at most 168 VGPRs each.
-template <typename T, int RULE, int W>
+// Two waves per SIMD at most (the LDS rings allow two workgroups of one compute wave per
+// compute unit, or one of two), so up to 256 VGPRs each.  TR: the launch records
+// traces; without it every trace branch is compiled out of the walk.
+template <typename T, int RULE, int W, bool TR>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * waves_for(W), 64 * waves_for(W)),
-                          amdgpu_waves_per_eu(3, 3)))
-void wf_sweep_kernel(KArgs a) {
+                          amdgpu_waves_per_eu(2, 2)))
+void wf_sweep_kernel(KArgs a_in) {
+  KArgs a = a_in;
+  if (!TR) {
+    a.trace = nullptr;
+    a.ctrace = nullptr;
+    a.ctrace_nc = 0;
+  }
   __shared__ WaveLds lds[W];
   __shared__ uint32_t s_item;
   const int wave = threadIdx.x >> 6;
@@ -1021,7 +1048,10 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
 
 template <typename T, int RULE, int W>
 hipError_t launch_t(int nwg, const KArgs& args, hipStream_t stream) {
-  hipLaunchKernelGGL((wf_sweep_kernel<T, RULE, W>), dim3(nwg), dim3(64 * waves_for(W)), 0, stream, args);
+  if (args.trace || args.ctrace)
+    hipLaunchKernelGGL((wf_sweep_kernel<T, RULE, W, true>), dim3(nwg), dim3(64 * waves_for(W)), 0, stream, args);
+  else
+    hipLaunchKernelGGL((wf_sweep_kernel<T, RULE, W, false>), dim3(nwg), dim3(64 * waves_for(W)), 0, stream, args);
   return hipGetLastError();
 }
 
@@ -1030,7 +1060,6 @@ hipError_t launch_w(int W, int nwg, const KArgs& args, hipStream_t stream) {
   switch (W) {
     case 1: return launch_t<T, RULE, 1>(nwg, args, stream);
     case 2: return launch_t<T, RULE, 2>(nwg, args, stream);
-    case 3: return launch_t<T, RULE, 3>(nwg, args, stream);
     default: return hipErrorInvalidValue;
   }
 }

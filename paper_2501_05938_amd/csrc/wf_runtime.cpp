@@ -166,9 +166,8 @@ int wfh::choose_waves(int64_t m) {
   return 1;
 }
 
-// At most 12 waves per compute unit (3 per SIMD at this kernel's register use), and the
-// LDS rings of W compute waves per workgroup.
-int wfh::wgs_per_cu(int W) { return W >= 2 ? 1 : 3; }
+// The LDS rings of one compute wave take about 65 KB of a compute unit's 160 KB.
+int wfh::wgs_per_cu(int W) { return W >= 2 ? 1 : 2; }
 
 uint32_t wfh::sentinel_of(int dtype) { return dtype == WF_F32 ? SENT_F32 : SENT_I32; }
 
@@ -500,7 +499,7 @@ static wf_status autotune(wf_ctx* ctx, const wf_problem* ps, int64_t count, int 
   WF_HIP(hipEventCreate(&e1));
   float best = -1.f;
   int bw = 1, bo = 1;
-  static const int Ws[] = {1, 2, 3};
+  static const int Ws[] = {1, 2};
   wf_status st = WF_OK;
   for (int W : Ws) {
     for (int order = 1; order <= 2 && st == WF_OK; ++order) {
@@ -547,7 +546,7 @@ extern "C" wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t
   if (t) tun = *t;
   for (int i = 0; i < 4; ++i)
     if (tun.reserved[i] != 0) return fail(WF_EINVAL, "wf_tuning.reserved must be 0");
-  if (tun.waves_per_wg < 0 || tun.waves_per_wg > 3) return fail(WF_EINVAL, "waves_per_wg must be 0, 1, 2 or 3");
+  if (tun.waves_per_wg < 0 || tun.waves_per_wg > 2) return fail(WF_EINVAL, "waves_per_wg must be 0, 1 or 2");
   if (tun.max_wgs < 0 || tun.order < 0 || tun.order > 2 || tun.use_graph < -1 || tun.use_graph > 1)
     return fail(WF_EINVAL, "bad tuning value");
   wf_status st = set_device(ctx);
