@@ -49,7 +49,7 @@ constexpr int CHUNK = 16;               // positions per IO chunk
 constexpr int SLOT = 64 * CHUNK * 4;    // bytes of one chunk slot (64 rows x 16 positions)
 constexpr int C_SLOTS = 8;              // chunk slots of the c ring
 constexpr int H_SLOTS = 8;              // chunk slots of the H ring (slack for the storer's jitter)
-constexpr int RING_T = 256;             // positions held by the T ring
+constexpr int RING_T = 512;             // positions held by the T ring
 // Inside a slot, the 16 bytes of row r, quad q (positions 4q..4q+3 of the chunk)
 // sit at (r/16)*1024 + (r%16)*64 + q*16: a 1024-byte block holds 16 whole rows of
 // the chunk.  A 64-lane LDS-DMA load (lane L -> byte 16L) then fills one block with
@@ -486,10 +486,13 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
     WF_CHUNK(1, k, cA, tA, cB, tB);
     WF_CHUNK(1, k + 1, cB, tB, cA, tA);
   }
-  for (; k < NCc; ++k) {
-    if ((k & 1) == 0) WF_CHUNK(2, k, cA, tA, cB, tB);
-    else WF_CHUNK(2, k, cB, tB, cA, tA);
+  // Tail, also in pairs: k is even here (both loops above step by two from 0), so
+  // chunk k uses set A and no branch on its parity forces register copies.
+  for (; k + 1 < NCc; k += 2) {
+    WF_CHUNK(2, k, cA, tA, cB, tB);
+    WF_CHUNK(2, k + 1, cB, tB, cA, tA);
   }
+  if (k < NCc) WF_CHUNK(2, k, cA, tA, cB, tB);
 #undef WF_CHUNK
   CBAR();
   if (lane == 0) {
@@ -899,29 +902,30 @@ __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds
 
 // Feed the T ring of compute wave 0 (positions 60 .. T_END) from the top
 // boundary (band 0) or from the handoff row of the band above.
+//
+// The handoff row is polled with two loads in flight, issued about half a round
+// trip apart, so new quads are seen about half a round trip sooner than with one.
+// A poll covers the next SMALL quads while the producer is ahead of it by less than
+// that (the usual case); when a poll comes back wholly valid the producer is far
+// ahead and the next poll covers up to 64 quads.
 template <typename T, int RULE, int W>
 __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds* lds, int lane, const KArgs& a) {
   const uint32_t SENT = Num<T>::SENT;
   const BandGeom B = band_geom<W>(g, band, 0);
   WaveLds& L = lds[0];
-  __amdgpu_buffer_rsrc_t hand_in =
-      make_rsrc(g.hand + (band > 0 ? (int64_t)(band - 1) * g.hand_ld : 0), (uint32_t)(g.hand_ld * 4));
   int tw = 60;
   Watch t_idle;
   uint32_t polls = 0;
-  while (tw < B.T_END) {
-    int limit = (int)ld_ctl(&L.t_reset) + RING_T;
-    if (limit > B.T_END) limit = B.T_END;
-    CBAR();
-    int got = 0;
-    if (tw < limit) {
-      const int nq = (limit - tw) / 4;
-      const int p = tw + 4 * lane;
-      const bool mine = lane < nq && lane < 16;
-      u4 v = {SENT, SENT, SENT, SENT};
-      bool valid = false;
-      if (mine) {
-        if (band == 0) {
+  if (band == 0) {
+    while (tw < B.T_END) {
+      int limit = (int)ld_ctl(&L.t_reset) + RING_T;
+      if (limit > B.T_END) limit = B.T_END;
+      CBAR();
+      if (tw < limit) {
+        const int nq = (limit - tw) / 4;
+        const int p = tw + 4 * lane;
+        if (lane < nq) {
+          u4 v;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int64_t ti = (int64_t)p + e - 62;  // index into top[] (= column + 1)
@@ -932,29 +936,77 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
             }
             v[e] = bits(val);
           }
-          valid = true;
-        } else {
-          v = __builtin_amdgcn_raw_buffer_load_b128(hand_in, p * 4, 0, CPOL_SC1);
-          valid = v.x != SENT && v.y != SENT && v.z != SENT && v.w != SENT;
+          lds_st4(L8(L.tring) + (p & (RING_T - 1)) * 4, v);
         }
-      }
-      const uint64_t ok = __builtin_amdgcn_ballot_w64(valid);
-      const int nvalid = (int)__builtin_ctzll(~ok);  // leading run of valid quads
-      if (nvalid > 0) {
-        if (lane < nvalid) lds_st4(L8(L.tring) + (p & (RING_T - 1)) * 4, v);
-        tw += 4 * nvalid;
-        got = nvalid;
+        tw += 4 * (nq < 64 ? nq : 64);
         __builtin_amdgcn_s_waitcnt(0xc07f);
         CBAR();
         if (lane == 0) st_ctl(&L.t_fed, (uint32_t)tw);
+        t_idle.reset();
+        continue;
       }
+      if (!io_idle<true>(lds, a, t_idle, polls)) return;
     }
+    return;
+  }
+  constexpr int SMALL = 8;
+  const __amdgpu_buffer_rsrc_t hand_in = make_rsrc(g.hand + (int64_t)(band - 1) * g.hand_ld, (uint32_t)(g.hand_ld * 4));
+  int want = SMALL;
+  // Poll: quads [base, base + 4 nq) of the handoff row (nq = 0: nothing issued).
+  auto issue = [&](u4& v, int& base, int& nq) {
+    int limit = (int)ld_ctl(&L.t_reset) + RING_T;
+    if (limit > B.T_END) limit = B.T_END;
+    base = tw;
+    nq = (limit - tw) / 4;
+    if (nq > want) nq = want;
+    if (nq < 0) nq = 0;
+    // Every lane issues the load (lanes past nq at an out-of-range offset, which reads
+    // zeros without touching memory), so no branch separates the two polls and the
+    // wait before a poll is used counts only the loads issued after it.
+    const uint32_t off = lane < nq ? (uint32_t)((base + 4 * lane) * 4) : 0x80000000u;
+    v = __builtin_amdgcn_raw_buffer_load_b128(hand_in, off, 0, CPOL_SC1);
+    // Keep the other poll's checks below this load (else waiting for them would also
+    // wait for this load).
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  // Take the leading run of valid quads at positions >= tw from a returned poll.
+  auto consume = [&](const u4& v, int base, int nq) -> int {
+    const int off = (tw - base) / 4;  // quads of this poll already taken from the other one
+    const bool valid = lane >= off && lane < nq && v.x != SENT && v.y != SENT && v.z != SENT && v.w != SENT;
+    const uint64_t m = __builtin_amdgcn_ballot_w64(valid) >> (off < 64 ? off : 63);
+    if (off >= nq) return 0;
+    // ~m is 0 only when all 64 lanes of the poll are valid (off = 0, nq = 64).
+    const int nvalid = ~m == 0ull ? 64 : (int)__builtin_ctzll(~m);
+    if (nvalid == 0) {
+      want = SMALL;
+      return 0;
+    }
+    if (lane >= off && lane < off + nvalid) lds_st4(L8(L.tring) + ((base + 4 * lane) & (RING_T - 1)) * 4, v);
+    tw += 4 * nvalid;
+    want = nvalid == nq - off ? 64 : SMALL;
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    CBAR();
+    if (lane == 0) st_ctl(&L.t_fed, (uint32_t)tw);
+    return nvalid;
+  };
+  u4 vA, vB;
+  int bA, nA, bB, nB;
+  issue(vA, bA, nA);
+  __builtin_amdgcn_s_sleep(8);
+  for (;;) {
+    issue(vB, bB, nB);
+    int got = consume(vA, bA, nA);
+    if (tw >= B.T_END) break;
+    issue(vA, bA, nA);
+    got += consume(vB, bB, nB);
+    if (tw >= B.T_END) break;
     if (got) {
       t_idle.reset();
-      continue;
+    } else if (!io_idle<true>(lds, a, t_idle, polls)) {
+      break;
     }
-    if (!io_idle<true>(lds, a, t_idle, polls)) return;
   }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // no poll still landing in registers at exit
 }
 
 // ------------------------------------------------------------------ kernel
