@@ -132,6 +132,16 @@ __device__ __forceinline__ void shift_in_lane63(u4& acc, const u4& h) {
     acc[e] = (uint32_t)__builtin_amdgcn_update_dpp((int)h[e], (int)acc[e], 0x101, 0xf, 0xf, false);
 }
 
+// Four absent boundary values (the T ring's padding past a band's last T position).
+template <typename T, int RULE> __device__ __forceinline__ u4 absent4() {
+  const uint32_t v = bits(Num<T>::template absent<RULE>());
+  return u4{v, v, v, v};
+}
+
+// End of the T positions a walk of G groups reads: its last chunk (number NC - 1, NC =
+// ceil(4G / 16)) checks positions up to 16 (NC - 1) + 64 + 16.
+__host__ __device__ constexpr int t_pad_end(int G) { return CHUNK * ((4 * G + CHUNK - 1) / CHUNK) + 64; }
+
 template <typename T> __device__ __forceinline__ T dpp_shr1(T old, T src) {
   return from_bits<T>((uint32_t)__builtin_amdgcn_update_dpp((int)bits(old), (int)bits(src), 0x138, 0xf, 0xf, false));
 }
@@ -315,9 +325,11 @@ __device__ __forceinline__ void snap_ctl(WaveLds& L, WaveLds* C, CtlSnap& s) {
 // without branches): when the producer is not that far yet, the chunk waits for the
 // chunk's last quad, which the producer writes after the others.
 // KIND 0: the first four chunks, where lanes left of column 0 keep their boundary value;
-// KIND 1: interior (this chunk's and the next chunk's groups all lie below gT);
-// KIND 2: tail.  CONS: 0 = no consumer, 1 = the next compute wave (LDS), 2 = the next
-// band (global handoff row).
+// KIND 1: every later chunk.  The T ring is fed past the band's last T position with
+// absent values, so KIND 1 chunks read and check all four quads; groups past the last
+// one (g >= G) compute cells right of the grid, which nothing stores or reads.
+// CONS: 0 = no consumer, 1 = the next compute wave (LDS), 2 = the next band (global
+// handoff row).
 template <typename T, int RULE, int KIND, int CONS>
 __device__ __forceinline__ void compute_chunk(
     int k, int G, int gT, int NCc, WaveLds* lds, WaveLds& L, WaveLds* C,
@@ -402,7 +414,7 @@ __device__ __forceinline__ void compute_chunk(
     CBAR();
     if (lane == 0) st_ctl(&L.t_reset, (uint32_t)(pos + 64 + 4 * nq));
   }
-  read_chunk<KIND == 1 ? 1 : 0>(k + 1, gT, crow, tr_base, cn, tn);
+  read_chunk<1>(k + 1, gT, crow, tr_base, cn, tn);
   lds_u8* hb = hrow + (k % H_SLOTS) * SLOT;
   lds_u8* ct = ct_base + (pos & (RING_T - 1)) * 4;
   // Bottom-row quads of the chunk for the next band, gathered into lanes 60..63 (lane 63
@@ -412,7 +424,6 @@ __device__ __forceinline__ void compute_chunk(
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int g = 4 * k + q;
-    if (KIND == 2 && g >= G) break;
     // The next chunk start's checks, read while this last group runs.
     if (q == 3) snap_ctl<CONS>(L, C, snap);
     const u4 cv = cc[q];
@@ -432,16 +443,16 @@ __device__ __forceinline__ void compute_chunk(
     // H into the ring, bottom row to the consumer.  Positions < 60 are never read by a consumer.
     lds_st4(hb + QUAD * q, h4);
     if (CONS == 1 && (KIND != 0 || g >= 15)) {
-      if (lane63) lds_st4(ct + 16 * q, h4);
+      // Past the last group the consumer's ring gets absent values (its padding).
+      if (lane63) lds_st4(ct + 16 * q, g < G ? h4 : absent4<T, RULE>());
     }
     if (CONS == 2) shift_in_lane63(hand4, h4);
   }
   if (CONS == 2) {
-    // Group of lane 60..63's quad; positions below 60 are never read by a consumer and
-    // stay at the sentinel.
-    const int nq = KIND == 2 ? (G - 4 * k < 4 ? G - 4 * k : 4) : 4;
-    const int g = 4 * k + nq - 1 - (63 - lane);
-    if (lane >= 60 && g >= 4 * k && (KIND != 0 || g >= 15))
+    // Lane 60+q holds group 4k+q's quad.  Only positions [60, 4G) are written: the
+    // others are never read by a consumer and stay at the sentinel.
+    const int g = 4 * k + lane - 60;
+    if (lane >= 60 && g < G && (KIND != 0 || g >= 15))
       __builtin_amdgcn_raw_buffer_store_b128(hand4, hand_out, 16 * g, 0, CPOL_SC1);
   }
 }
@@ -467,7 +478,7 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   u4 cA[4], tA[4], cB[4], tB[4];
   wait_until<false>([&] { return ld_ctl(&L.c_ready) >= 1u; }, lds, a);
   CBAR();
-  read_chunk<0>(0, gT, crow, L8(L.tring), cA, tA);
+  read_chunk<1>(0, gT, crow, L8(L.tring), cA, tA);
 #pragma unroll
   for (int q = 0; q < 4; ++q) tB[q] = tA[q];
   CtlSnap snap;
@@ -481,24 +492,28 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
     WF_CHUNK(0, k, cA, tA, cB, tB);
     WF_CHUNK(0, k + 1, cB, tB, cA, tA);
   }
-  // Interior, two chunks per pass so the register sets alternate without copies.
-  for (; 4 * k + 12 <= gT; k += 2) {
+  // Every later chunk, two per pass so the register sets alternate without copies (k is
+  // even here, so a last odd chunk uses set A).
+  for (; k + 1 < NCc; k += 2) {
     WF_CHUNK(1, k, cA, tA, cB, tB);
     WF_CHUNK(1, k + 1, cB, tB, cA, tA);
   }
-  // Tail, also in pairs: k is even here (both loops above step by two from 0), so
-  // chunk k uses set A and no branch on its parity forces register copies.
-  for (; k + 1 < NCc; k += 2) {
-    WF_CHUNK(2, k, cA, tA, cB, tB);
-    WF_CHUNK(2, k + 1, cB, tB, cA, tA);
-  }
-  if (k < NCc) WF_CHUNK(2, k, cA, tA, cB, tB);
+  if (k < NCc) WF_CHUNK(1, k, cA, tA, cB, tB);
 #undef WF_CHUNK
+  const int t_pad = t_pad_end(G);
+  if (CONS == 1) {
+    // The consumer's last chunks read T positions [16 NCc, t_pad), past every group of
+    // this walk: fill them with absent values once its ring has room.
+    wait_until<false>([&] { return (int)ld_ctl(&C->t_reset) + RING_T >= t_pad; }, lds, a);
+    CBAR();
+    const int p = CHUNK * NCc + 4 * lane;
+    if (p < t_pad) lds_st4(L8(C->tring) + (p & (RING_T - 1)) * 4, absent4<T, RULE>());
+  }
   CBAR();
   if (lane == 0) {
     st_ctl(&L.progress, (uint32_t)(4 * G));
     // Every T position this walk reads has been consumed: release the producer's tail.
-    st_ctl(&L.t_reset, (uint32_t)(4 * G));
+    st_ctl(&L.t_reset, (uint32_t)t_pad);
   }
 }
 
@@ -874,7 +889,8 @@ __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds
       if (ks[j] < B[j].NC) done = false;
     }
     if (rearm_hand) {
-      const int fed = (int)ld_ctl(&lds[0].t_fed);
+      int fed = (int)ld_ctl(&lds[0].t_fed);
+      if (fed > hand_end) fed = hand_end;  // positions past the handoff row are padding
       if (fed > hr) {
         const int nq = (fed - hr) / 4;
         for (int base = 0; base < nq; base += 64) {
@@ -901,7 +917,8 @@ __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds
 }
 
 // Feed the T ring of compute wave 0 (positions 60 .. T_END) from the top
-// boundary (band 0) or from the handoff row of the band above.
+// boundary (band 0) or from the handoff row of the band above, then pad it with
+// absent values up to t_pad_end(G), the last position the walk's chunks check.
 //
 // The handoff row is polled with two loads in flight, issued about half a round
 // trip apart, so new quads are seen about half a round trip sooner than with one.
@@ -916,10 +933,11 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
   int tw = 60;
   Watch t_idle;
   uint32_t polls = 0;
+  const int t_pad = t_pad_end(B.G);
   if (band == 0) {
-    while (tw < B.T_END) {
+    while (tw < t_pad) {
       int limit = (int)ld_ctl(&L.t_reset) + RING_T;
-      if (limit > B.T_END) limit = B.T_END;
+      if (limit > t_pad) limit = t_pad;
       CBAR();
       if (tw < limit) {
         const int nq = (limit - tw) / 4;
@@ -955,24 +973,28 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
   // Poll: quads [base, base + 4 nq) of the handoff row (nq = 0: nothing issued).
   auto issue = [&](u4& v, int& base, int& nq) {
     int limit = (int)ld_ctl(&L.t_reset) + RING_T;
-    if (limit > B.T_END) limit = B.T_END;
+    if (limit > t_pad) limit = t_pad;
     base = tw;
     nq = (limit - tw) / 4;
     if (nq > want) nq = want;
     if (nq < 0) nq = 0;
-    // Every lane issues the load (lanes past nq at an out-of-range offset, which reads
-    // zeros without touching memory), so no branch separates the two polls and the
-    // wait before a poll is used counts only the loads issued after it.
-    const uint32_t off = lane < nq ? (uint32_t)((base + 4 * lane) * 4) : 0x80000000u;
+    // Every lane issues the load (lanes past nq or past the handoff row at an
+    // out-of-range offset, which reads zeros without touching memory), so no branch
+    // separates the two polls and the wait before a poll is used counts only the loads
+    // issued after it.
+    const int p = base + 4 * lane;
+    const uint32_t off = lane < nq && p < B.T_END ? (uint32_t)(p * 4) : 0x80000000u;
     v = __builtin_amdgcn_raw_buffer_load_b128(hand_in, off, 0, CPOL_SC1);
     // Keep the other poll's checks below this load (else waiting for them would also
     // wait for this load).
     __builtin_amdgcn_sched_barrier(0);
   };
   // Take the leading run of valid quads at positions >= tw from a returned poll.
-  auto consume = [&](const u4& v, int base, int nq) -> int {
+  auto consume = [&](u4& v, int base, int nq) -> int {
     const int off = (tw - base) / 4;  // quads of this poll already taken from the other one
-    const bool valid = lane >= off && lane < nq && v.x != SENT && v.y != SENT && v.z != SENT && v.w != SENT;
+    const bool pad = base + 4 * lane >= B.T_END;
+    if (pad) v = absent4<T, RULE>();
+    const bool valid = lane >= off && lane < nq && (pad || (v.x != SENT && v.y != SENT && v.z != SENT && v.w != SENT));
     const uint64_t m = __builtin_amdgcn_ballot_w64(valid) >> (off < 64 ? off : 63);
     if (off >= nq) return 0;
     // ~m is 0 only when all 64 lanes of the poll are valid (off = 0, nq = 64).
@@ -996,10 +1018,10 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
   for (;;) {
     issue(vB, bB, nB);
     int got = consume(vA, bA, nA);
-    if (tw >= B.T_END) break;
+    if (tw >= t_pad) break;
     issue(vA, bA, nA);
     got += consume(vB, bB, nB);
-    if (tw >= B.T_END) break;
+    if (tw >= t_pad) break;
     if (got) {
       t_idle.reset();
     } else if (!io_idle<true>(lds, a, t_idle, polls)) {
