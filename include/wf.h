@@ -127,9 +127,9 @@ wf_status wf_solve(wf_ctx* ctx, const wf_problem* p, void* stream);
  * All grids of one call share dtype and rule (WF_EUNSUPPORTED otherwise).
  * Autotuning: when `t` is NULL or leaves both waves_per_wg and order at 0 (and
  * use_graph is not -1), the first call for a batch shape (count, sizes, dtype,
- * rule, mode) runs the batch once per candidate configuration (waves per
- * workgroup 1, 2, 3 x grid-major / interleaved order), synchronously, timed
- * on `stream`, and keeps the fastest in the context's tuning table; later
+ * rule, mode) runs the batch twice per candidate configuration (waves per
+ * workgroup 1, 2 x grid-major / interleaved order), synchronously, timing the
+ * second run on `stream`, and keeps the fastest in the context's tuning table; later
  * calls with that shape use it.  Every trial writes the full, correct result.
  * With use_graph = 1 the chosen launch is captured in a hipGraph and replayed
  * when the same batch shape is solved again. */
