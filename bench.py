@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 65536x65536 edges-mode run")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -123,6 +124,32 @@ def cpu_baseline(seconds: float):
     return {"value": done_cells / spent, "unit": "cells/s", "cores": 1, "kind": "oracle",
             "sample": f"fp64 oracle loop over {done_cells // N} rows of the {M}x{N} seed-{SEED} grid "
                       f"in {band}-row bands ({spent:.1f} s of one core)"}
+
+
+def large_edges(torch, wf, wfgen, steps=3):
+    """The 65536 x 65536 grid (17 GB of fp32 input, device-resident) in edges mode: only
+    the last row, last column and final cell are written."""
+    m = n = 65536
+    c = torch.empty((m, n), dtype=torch.float32, device="cuda")
+    wfgen.fill_device(c, seed=3)
+    lr = torch.empty(n, dtype=torch.float32, device="cuda")
+    lc = torch.empty(m, dtype=torch.float32, device="cuda")
+    fc = torch.empty(1, dtype=torch.float32, device="cuda")
+    run = lambda: wf.solve(c, mode="edges", last_row=lr, last_col=lc, final_cell=fc)  # noqa: E731
+    run()
+    torch.cuda.synchronize()
+    wf.check()
+    per = time_events(torch, run, steps, torch.cuda.current_stream())
+    wf.check()
+    kms = sum(per) / len(per)
+    alg = 4.0 * m * n + 4.0 * (m + n) + 4.0
+    achieved = alg / (kms * 1e-3) / 1e9
+    del c, lr, lc, fc
+    torch.cuda.empty_cache()
+    return {"workload": "single 65536x65536 grid, fp32, min rule, edges mode (last row, last column, final cell)",
+            "seed": 3, "steps": steps, "kernel_ms": kms, "cells_per_s": m * n / (kms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": alg, "bytes_per_cell": 4}}
 
 
 def batched(torch, wf, wfgen, count):
@@ -325,6 +352,12 @@ def main():
                      "kernel_ms": kernel_ms, "kernel_ms_min": min(per),
                      "bytes_per_launch": alg_bytes, "bytes_per_cell": 8},
     }
+    if not args.no_large:
+        log("[bench] 65536x65536 edges mode")
+        try:
+            result["large_edges"] = large_edges(torch, wf, wfgen)
+        except Exception as e:  # report, do not lose the main line
+            result["large_edges"] = {"error": repr(e)}
     if not args.no_batched:
         log(f"[bench] batched: {args.batch_count} grids")
         try:

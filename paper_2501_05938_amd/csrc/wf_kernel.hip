@@ -446,7 +446,10 @@ __device__ __forceinline__ void compute_chunk(
       // Past the last group the consumer's ring gets absent values (its padding).
       if (lane63) lds_st4(ct + 16 * q, g < G ? h4 : absent4<T, RULE>());
     }
-    if (CONS == 2) shift_in_lane63(hand4, h4);
+    if (CONS == 2) {
+      if (q == 0) hand4 = h4;  // lane 63 holds group 0's quad; the other lanes' values are shifted out
+      else shift_in_lane63(hand4, h4);
+    }
   }
   if (CONS == 2) {
     // Lane 60+q holds group 4k+q's quad.  Only positions [60, 4G) are written: the

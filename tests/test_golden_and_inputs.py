@@ -57,3 +57,11 @@ def test_oracle_reproduces_golden():
             assert lc32.view(np.uint32).tolist() == exp["f32_last_col_bits"]
             lri, lci = oracle.sweep(ci, rule, "i64", full=False)
             assert lri.tolist() == exp["i64_last_row"] and lci.tolist() == exp["i64_last_col"]
+
+
+def test_numpy_integer_seed_equals_python_int_seed():
+    # Seeds drawn from numpy (e.g. a sampled grid index) must give the same stream.
+    import numpy as np
+
+    assert np.array_equal(wfgen.cells(np.int64(1006), 7, 9), wfgen.cells(1006, 7, 9))
+    assert np.array_equal(wfgen.cells(np.uint32(5), 4, 4, "i32"), wfgen.cells(5, 4, 4, "i32"))

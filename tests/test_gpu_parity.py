@@ -169,3 +169,25 @@ def test_full_size_16384_against_fp32_oracle():
     for r in rows:
         k = (r + np.arange(n) + 1).astype(np.float64)
         assert (np.abs(got[r].astype(np.float64) - exp64[r]) <= k * U / (1 - k * U) * exp64[r]).all()
+
+
+@pytest.mark.slow
+def test_full_size_65536_edges_against_fp32_oracle():
+    """The 65536 x 65536 configuration (17 GB input, device-resident) in edges mode, as
+    the benchmark launches it: last row, last column and final cell bit-exact against
+    the fp32 oracle, swept band by band on the host from the same generated input."""
+    m = n = 65536
+    print("[parity] 65536^2 edges", flush=True)
+    cd = torch.empty((m, n), dtype=torch.float32, device=DEV)
+    wfgen.fill_device(cd, seed=3)
+    lr, lc, fc = wf.solve(cd, mode="edges")
+    got_lr, got_lc, got_fc = _host(lr), _host(lc), _host(fc)
+    wf.check()
+
+    def rows(row0, nrows):
+        return cd[row0:row0 + nrows].cpu().numpy()
+
+    exp_lr, exp_lc, _ = oracle.sweep_banded(rows, m, n, "min", "f32", band=2048)
+    assert np.array_equal(got_lr.view(np.uint32), exp_lr.view(np.uint32))
+    assert np.array_equal(got_lc.view(np.uint32), exp_lc.view(np.uint32))
+    assert got_fc.view(np.uint32)[0] == exp_lr.view(np.uint32)[-1]

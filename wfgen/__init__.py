@@ -34,7 +34,7 @@ def splitmix64(seed: int, k: np.ndarray) -> np.ndarray:
     """k-th outputs (uint64 array) of the SplitMix64 stream seeded with `seed`."""
     k = np.asarray(k, dtype=np.uint64)
     with np.errstate(over="ignore"):
-        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + (k + np.uint64(1)) * GAMMA
+        z = np.uint64(int(seed) & 0xFFFFFFFFFFFFFFFF) + (k + np.uint64(1)) * GAMMA
         z = (z ^ (z >> np.uint64(30))) * _M1
         z = (z ^ (z >> np.uint64(27))) * _M2
         z = z ^ (z >> np.uint64(31))
