@@ -291,18 +291,17 @@ __device__ __noinline__ u4 wait_quad(const lds_u8* tp, WaveLds* lds, uint32_t* c
   return q;
 }
 
-// Reads of chunk kn's inputs for one lane: its four c quads and (groups below gT) its
-// four T quads.  A read past the last chunk only picks up unused stale data.
-template <int KIND>
-__device__ __forceinline__ void read_chunk(int kn, int gT, const lds_u8* crow, const lds_u8* tr_base,
-                                           u4 (&c)[4], u4 (&t)[4]) {
+// Reads of chunk kn's inputs for one lane: its four c quads and its four T quads (the
+// T ring is fed up to the padding past the band's last position, so every chunk has
+// four).  A read past the last chunk only picks up unused stale data.
+__device__ __forceinline__ void read_chunk(int kn, const lds_u8* crow, const lds_u8* tr_base, u4 (&c)[4],
+                                           u4 (&t)[4]) {
   const lds_u8* cb = crow + (kn % C_SLOTS) * SLOT;
   const int tpos = (CHUNK * kn + 64) & (RING_T - 1);
 #pragma unroll
   for (int q = 0; q < 4; ++q) c[q] = lds_ld4(cb + QUAD * q);
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (KIND == 1 || 4 * kn + q < gT) t[q] = lds_ld4(tr_base + (tpos + 4 * q) * 4);
+  for (int q = 0; q < 4; ++q) t[q] = lds_ld4(tr_base + (tpos + 4 * q) * 4);
 }
 
 // Control words a chunk start checks, read ahead of time.  The counters only grow, so
@@ -414,7 +413,7 @@ __device__ __forceinline__ void compute_chunk(
     CBAR();
     if (lane == 0) st_ctl(&L.t_reset, (uint32_t)(pos + 64 + 4 * nq));
   }
-  read_chunk<1>(k + 1, gT, crow, tr_base, cn, tn);
+  read_chunk(k + 1, crow, tr_base, cn, tn);
   lds_u8* hb = hrow + (k % H_SLOTS) * SLOT;
   lds_u8* ct = ct_base + (pos & (RING_T - 1)) * 4;
   // Bottom-row quads of the chunk for the next band, gathered into lanes 60..63 (lane 63
@@ -481,7 +480,7 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   u4 cA[4], tA[4], cB[4], tB[4];
   wait_until<false>([&] { return ld_ctl(&L.c_ready) >= 1u; }, lds, a);
   CBAR();
-  read_chunk<1>(0, gT, crow, L8(L.tring), cA, tA);
+  read_chunk(0, crow, L8(L.tring), cA, tA);
 #pragma unroll
   for (int q = 0; q < 4; ++q) tB[q] = tA[q];
   CtlSnap snap;
