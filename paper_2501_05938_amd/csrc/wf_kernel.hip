@@ -8,7 +8,7 @@
 //   waits on a band with a smaller ticket, which is held by a running
 //   workgroup.  A workgroup holds W compute waves (64 rows each, lane r owns
 //   row r) and staging waves that never mix load and store traffic: one
-//   loader per compute wave, one storer per two compute waves and one feeder.
+//   loader and one storer per compute wave, and one feeder.
 //
 // Compute wave (the hot loop)
 //   Lane r handles column t - r at step t, so each step advances a 64-cell
@@ -20,16 +20,19 @@
 //   Inputs c come from an LDS ring filled by the loader, stored skewed
 //   (row r, position p holds column p - r) so that all lanes read the same
 //   position with one aligned 16-byte load per 4 steps; H goes to a second
-//   LDS ring in the same layout.  Rows are padded by 16 bytes so the 64
-//   lanes' 16-byte accesses spread over the LDS banks.  The compute wave
-//   issues no vector-memory loads, so it never waits on memory counters.
+//   LDS ring in the same layout.  The walk goes in chunks of 16 steps: the
+//   control words and the chunk's T quads are checked once at its start, and
+//   the next chunk's inputs are read while it runs.  The compute wave issues
+//   no vector-memory loads, so it never waits on memory counters.
 //
 // Handoff of the bottom row (the N of the next strip's lane 0)
 //   Inside a workgroup, lane 63 of compute wave w writes its 4 values of each
 //   step group into the T ring of wave w+1 (LDS).  Across workgroups, the last
-//   compute wave writes them to a global handoff row with device-coherent
-//   (sc1) stores, and the feeder of the next band copies them into the T ring
-//   of its compute wave 0.
+//   compute wave gathers a chunk's 16 values into lanes 60..63 and writes them
+//   to a global handoff row with one device-coherent (sc1) store, and the
+//   feeder of the next band polls that row and copies it into the T ring of
+//   its compute wave 0.  Past a band's last position the T ring is padded with
+//   absent values, so every chunk after the first four runs the same code.
 //   Validity is carried by the data itself: slots hold a sentinel until
 //   written, and a reader accepts a quad only when none of its four words is
 //   the sentinel (a 16-byte read racing a 16-byte write may see part of it).
@@ -373,7 +376,8 @@ __device__ __forceinline__ void compute_chunk(
   CBAR();
   const lds_u8* tr_base = L8(L.tring);
   const int tpos = (pos + 64) & (RING_T - 1);  // T ring position of group 4k's quad
-  // Validate the chunk's T quads (those of groups below gT).  All four words of a quad
+  // Validate the chunk's T quads (all four; in the first four chunks, those of groups
+  // below gT, whose quads hold columns of the grid).  All four words of a quad
   // are checked: a 16-byte LDS read racing a 16-byte write from another wave may see
   // part of it.  All lanes read the same quads, so the test is wave-uniform.
   if (KIND == 1 || 4 * k < gT) {
@@ -555,8 +559,8 @@ __device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLd
 // and store traffic: on gfx9 the vector-memory counter does not return loads
 // and stores in order with respect to each other, so a wave holding both must
 // drain everything before it can use any loaded value.
-//   loader w : loads of c (register prefetch, DEPTH chunks ahead) -> c ring
-//   storer s : H stage-out, T-ring re-arming, handoff-row re-arming (stores only)
+//   loader w : LDS-DMA loads of c, up to C_SLOTS - 1 chunks ahead -> c ring
+//   storer w : H stage-out and handoff-row re-arming (stores only)
 //   feeder   : the T ring of compute wave 0, from the top boundary or from the
 //              band above (loads only)
 
