@@ -202,33 +202,53 @@ def solve(cost, out=None, rule: str = "min", top=None, left=None, mode: str = "f
     return last_row, last_col, final_cell
 
 
+class BatchPlan:
+    """A batch of grids marshalled once for repeated launches.
+
+    The wf_problem array is built when the plan is made; run() only calls
+    wf_solve_batched with it, so a batch solved again and again (a serving or
+    training loop over fixed buffers) pays no per-call argument marshalling.
+    The plan keeps the tensors it was made from alive.
+    """
+
+    def __init__(self, costs, outs=None, rule: str = "min", mode: str = "full",
+                 waves_per_wg: int = 0, max_wgs: int = 0, order: int = 0, use_graph: int = 1):
+        import torch
+        if outs is None:
+            outs = []
+            for c in costs:
+                m, n = c.shape
+                if mode == "full":
+                    outs.append(torch.empty((m, n), dtype=c.dtype, device=c.device))
+                else:
+                    outs.append((torch.empty(n, dtype=c.dtype, device=c.device),
+                                 torch.empty(m, dtype=c.dtype, device=c.device),
+                                 torch.empty(1, dtype=c.dtype, device=c.device)))
+        arr = (Problem * len(costs))()
+        for i, c in enumerate(costs):
+            if mode == "full":
+                arr[i] = make_problem(c, outs[i], rule, mode=mode)
+            else:
+                lr, lc, fc = outs[i]
+                arr[i] = make_problem(c, None, rule, mode=mode, last_row=lr, last_col=lc, final_cell=fc)
+        t = Tuning()
+        t.waves_per_wg, t.max_wgs, t.order, t.use_graph = waves_per_wg, max_wgs, order, use_graph
+        self.costs, self.outs = list(costs), outs
+        self._arr, self._tuning = arr, t
+        self._device = costs[0].device.index if costs else None
+
+    def run(self, stream=None):
+        """Launch the batch (asynchronous on `stream`); returns the outputs."""
+        _check(load_library().wf_solve_batched(context(self._device), self._arr, len(self.costs),
+                                               ctypes.byref(self._tuning), _stream_ptr(stream)))
+        return self.outs
+
+
 def solve_batched(costs, outs=None, rule: str = "min", mode: str = "full", stream=None,
                   waves_per_wg: int = 0, max_wgs: int = 0, order: int = 0, use_graph: int = 1):
     """Sweep many independent grids in one persistent launch.  Returns the list of outputs
     (H per grid in full mode, (last_row, last_col, final_cell) in edges mode)."""
-    import torch
-    if outs is None:
-        outs = []
-        for c in costs:
-            m, n = c.shape
-            if mode == "full":
-                outs.append(torch.empty((m, n), dtype=c.dtype, device=c.device))
-            else:
-                outs.append((torch.empty(n, dtype=c.dtype, device=c.device),
-                             torch.empty(m, dtype=c.dtype, device=c.device),
-                             torch.empty(1, dtype=c.dtype, device=c.device)))
-    arr = (Problem * len(costs))()
-    for i, c in enumerate(costs):
-        if mode == "full":
-            arr[i] = make_problem(c, outs[i], rule, mode=mode)
-        else:
-            lr, lc, fc = outs[i]
-            arr[i] = make_problem(c, None, rule, mode=mode, last_row=lr, last_col=lc, final_cell=fc)
-    t = Tuning()
-    t.waves_per_wg, t.max_wgs, t.order, t.use_graph = waves_per_wg, max_wgs, order, use_graph
-    dev = costs[0].device.index if costs else None
-    _check(load_library().wf_solve_batched(context(dev), arr, len(costs), ctypes.byref(t), _stream_ptr(stream)))
-    return outs
+    return BatchPlan(costs, outs, rule, mode, waves_per_wg, max_wgs, order, use_graph).run(stream)
 
 
 def check(device: int | None = None):

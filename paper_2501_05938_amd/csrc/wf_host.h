@@ -11,6 +11,7 @@
 #include <map>
 #include <string>
 #include <utility>
+#include <vector>
 
 // A launch slot owns everything one in-flight launch mutates: control words,
 // handoff rows, descriptor table and work list.  Slots are reused round-robin
@@ -33,6 +34,7 @@ struct GraphEntry {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   int slot = -1;
+  std::vector<wfk::GridDesc> descs;  // the descriptor table now in the slot's device copy
 };
 
 struct wf_ctx {

@@ -429,20 +429,27 @@ static wf_status batched_run(wf_ctx* ctx, const wf_problem* ps, int64_t count, i
     }
   }
   const uint32_t sent = sentinel_of(ps[0].dtype);
+  // Also on replay: a single-grid solve may have used this slot since, growing its
+  // handoff rows or arming them with another dtype's sentinel.
+  st = ensure_hand(*s, hand_total, sent, stream);
+  if (st != WF_OK) return st;
   if (!ge) {
-    st = ensure_hand(*s, hand_total, sent, stream);
-    if (st != WF_OK) return st;
     st = ensure_buf(&s->grids, &s->grids_cap, descs.size());
     if (st != WF_OK) return st;
     st = ensure_buf(&s->items, &s->items_cap, items.size());
     if (st != WF_OK) return st;
   }
   for (size_t gi = 0; gi < descs.size(); ++gi) descs[gi].hand = s->hand + hand_off[gi];
-  // The tables are copied on the stream (pointers may differ between calls with the same shape).
-  WF_HIP(hipMemcpyAsync(s->grids, descs.data(), descs.size() * sizeof(GridDesc), hipMemcpyHostToDevice, stream));
-  if (!ge) WF_HIP(hipMemcpyAsync(s->items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, stream));
-  // The host arrays must outlive the asynchronous copies.
-  WF_HIP(hipStreamSynchronize(stream));
+  // The tables are copied on the stream (pointers may differ between calls with the same
+  // shape); a replayed graph whose table is unchanged skips the copy.
+  const bool same_table = ge && ge->descs.size() == descs.size() &&
+                          std::memcmp(ge->descs.data(), descs.data(), descs.size() * sizeof(GridDesc)) == 0;
+  if (!same_table) {
+    WF_HIP(hipMemcpyAsync(s->grids, descs.data(), descs.size() * sizeof(GridDesc), hipMemcpyHostToDevice, stream));
+    if (!ge) WF_HIP(hipMemcpyAsync(s->items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, stream));
+    // The host arrays must outlive the asynchronous copies.
+    WF_HIP(hipStreamSynchronize(stream));
+  }
 
   KArgs a;
   std::memset(&a, 0, sizeof a);
@@ -469,6 +476,7 @@ static wf_status batched_run(wf_ctx* ctx, const wf_problem* ps, int64_t count, i
       if (err != hipSuccess) return fail(WF_EHIP, std::string("graph capture: ") + hipGetErrorString(err));
       ge = &(ctx->graphs[key] = e);
     }
+    if (!same_table) ge->descs = descs;
     WF_HIP(hipGraphLaunch(ge->exec, stream));
   } else {
     WF_HIP(launch_fill_u32(s->ctl, 0u, CTL_WORDS, stream));

@@ -120,3 +120,26 @@ def test_three_waves_per_workgroup_is_rejected():
     with pytest.raises(wf.WfError) as e:
         wf.solve_batched([a], waves_per_wg=3)
     assert e.value.status == -1  # WF_EINVAL
+
+
+def test_graph_replay_after_single_solves_of_another_dtype():
+    """A replayed batch whose launch slot was used meanwhile by single-grid int32
+    solves (other handoff-row sentinel, possibly larger rows) is still exact."""
+    shapes, hs, ds = _batch(16, 64, 300, seed=15)
+    outs = [torch.empty_like(d) for d in ds]
+    plan = wf.BatchPlan(ds, outs)
+    plan.run()
+    torch.cuda.synchronize()
+    ci = torch.from_numpy(wfgen.cells(16, 700, 700, "i32")).to(DEV)
+    for _ in range(10):  # cycles through every launch slot of the context
+        wf.solve(ci)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        print(f"[batched] replay after int32 solves {rep}", flush=True)
+        for o in outs:
+            o.fill_(float("nan"))
+        plan.run()
+        torch.cuda.synchronize()
+        wf.check()
+        for (m, n), h, o in zip(shapes, hs, outs):
+            assert np.array_equal(_bits(o), _expect(h, "min", "f32")), (m, n, rep)
