@@ -398,6 +398,16 @@ def main():
             result["serving"] = serving(torch, wf, wfgen, args.serve_grids, args.serve_requests, args.serve_load)
         except Exception as e:  # report, do not lose the main line
             result["serving"] = {"error": repr(e)}
+        # The same mix at a light and a heavy load (half as many requests each).
+        others = {}
+        for load in (0.3, 0.9):
+            log(f"[bench] serving at load {load}")
+            try:
+                r = serving(torch, wf, wfgen, args.serve_grids, max(args.serve_requests // 2, 1), load)
+                others[str(load)] = {k: r[k] for k in ("requests", "rate_req_per_s", "p50_ms", "p99_ms", "cells_per_s")}
+            except Exception as e:  # report, do not lose the main line
+                others[str(load)] = {"error": repr(e)}
+        result["serving"]["other_loads"] = others
     if not args.no_cpu:
         log(f"[bench] cpu baseline ({args.cpu_seconds:.0f} s of one core)")
         result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
