@@ -530,6 +530,9 @@ __device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLd
   const int64_t m = g.m, n = g.n;
   const int64_t row0 = (int64_t)band * (64 * W) + 64 * w;
   if (row0 >= m) return;
+  // The walk is the critical path: let it win the compute unit's shared units (LDS,
+  // scalar and instruction issue) over the staging waves.
+  __builtin_amdgcn_s_setprio(3);
   const int G = (int)groups_for(n);
   const int gT = n >= 2 ? (int)((n - 2) / 4 + 1) : 0;
   const bool lds_consumer = (w + 1 < W && row0 + 64 < m);
