@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--serve-grids", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-inflight", type=int, default=4, help="server launches in flight")
+    ap.add_argument("--serve-batch", type=int, default=256, help="server requests per launch at most")
     ap.add_argument("--copy-ref", action="store_true",
                     help="run one plain 1 GiB device-to-device copy first: a kernel of known HBM "
                          "traffic (1 GiB read + 1 GiB written) to scale memory counters by")
@@ -215,7 +217,7 @@ def batched(torch, wf, wfgen, count):
             "shapes": "m, n independently log-uniform in [64, 2048] (PCG64 seed 4), grid g seed 1000+g"}
 
 
-def serving(torch, wf, wfgen, grids, requests, load):
+def serving(torch, wf, wfgen, grids, requests, load, inflight=4, batch=256):
     """Poisson arrivals of square grids (n log-uniform in [128, 8192]) served under a
     64 GiB budget with continuous batching.  The arrival rate is `load` times the
     batched capacity for the same mix, measured first with one wf_solve_batched
@@ -246,7 +248,7 @@ def serving(torch, wf, wfgen, grids, requests, load):
     rate = load * cap
     arrivals = [a / rate for (a, _, _) in reqs]
     lat, cells_done = [], 0
-    with wf.Server(budget_bytes=64 << 30, max_inflight=4, max_batch=256) as srv:
+    with wf.Server(budget_bytes=64 << 30, max_inflight=inflight, max_batch=batch) as srv:
         # warm-up: one request of each distinct grid is not needed; a short burst warms the path
         for g in range(min(8, grids)):
             tk = srv.submit(costs[g])
@@ -306,7 +308,8 @@ def serving(torch, wf, wfgen, grids, requests, load):
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "cells_per_s": cells_done / span,
             "submit_lag_p99_ms": float(np.percentile(np.array(lag) * 1e3, 99)),
-            "peak_server_bytes": peak, "budget_bytes": 64 << 30, "checked_equal_alone": checked}
+            "peak_server_bytes": peak, "budget_bytes": 64 << 30, "checked_equal_alone": checked,
+            "max_inflight": inflight, "max_batch": batch}
 
 
 def main():
@@ -395,7 +398,8 @@ def main():
     if not args.no_serving:
         log(f"[bench] serving: {args.serve_requests} requests over {args.serve_grids} grids")
         try:
-            result["serving"] = serving(torch, wf, wfgen, args.serve_grids, args.serve_requests, args.serve_load)
+            result["serving"] = serving(torch, wf, wfgen, args.serve_grids, args.serve_requests, args.serve_load,
+                                        args.serve_inflight, args.serve_batch)
         except Exception as e:  # report, do not lose the main line
             result["serving"] = {"error": repr(e)}
         # The same mix at a light and a heavy load (half as many requests each).
@@ -403,7 +407,8 @@ def main():
         for load in (0.3, 0.9):
             log(f"[bench] serving at load {load}")
             try:
-                r = serving(torch, wf, wfgen, args.serve_grids, max(args.serve_requests // 2, 1), load)
+                r = serving(torch, wf, wfgen, args.serve_grids, max(args.serve_requests // 2, 1), load,
+                            args.serve_inflight, args.serve_batch)
                 others[str(load)] = {k: r[k] for k in ("requests", "rate_req_per_s", "p50_ms", "p99_ms", "cells_per_s")}
             except Exception as e:  # report, do not lose the main line
                 others[str(load)] = {"error": repr(e)}
