@@ -191,6 +191,62 @@ wf_status wf_server_destroy(wf_server* s);
 /* Bytes of device memory currently held for requests, and the peak so far. */
 wf_status wf_server_memory(wf_server* s, int64_t* in_use, int64_t* peak);
 
+/* ------------------------------------------ launch-concurrency (stream) model
+ * The model of arXiv 2501.05938, Sections 2.3-2.4 (Eqs. 3-7) and the selection
+ * rule of Section 3, used here to choose how many streams the per-grid path
+ * (wf_solve_each) spreads its launches over.  Host-only: no device call.
+ *
+ * A sample is one timed job: `size` is the problem size (the paper's SLAE size;
+ * for the per-grid path, the cells of all grids of the job), `streams` the
+ * stream count s, `t_str` its time on s streams, `t_non_str` the same job on one
+ * stream, and `sum` the time of the operations the streams overlap (the paper's
+ * Eq. 3; here the device time of the job's kernels run one after another).
+ * All times in milliseconds. */
+typedef struct wf_stream_sample {
+  double size;
+  int32_t streams;           /* >= 1 */
+  int32_t reserved;          /* ignored */
+  double t_str, t_non_str, sum;
+} wf_stream_sample;
+
+typedef struct wf_stream_model {
+  double sum_slope, sum_intercept;  /* Eq. 4: sum = sum_slope * size + sum_intercept */
+  double split_size;                /* Eq. 7 regimes: small for size <= split_size, big above */
+  double small[3];                  /* Eq. 7 small: small[0]*size + small[1]*log10(s) + small[2] */
+  double big[3];                    /* Eq. 7 big: (big[0]*size + big[1]) * log2(s^(4/3)) + big[2] */
+} wf_stream_model;
+
+typedef struct wf_fit_report {
+  double r2_train, r2_test;         /* 1 - SS_res / SS_tot on each half of the 3:1 split */
+  double mse_train, mse_test;       /* SS_res / samples */
+  int64_t n_train, n_test;
+} wf_fit_report;
+
+/* Fit the model to `count` samples (Section 2.4).
+ *   Eq. 4 is fitted on one point per distinct size (sizes in order of first
+ *   appearance; its sum is the mean of that size's samples); Eq. 5 turns every
+ *   sample with streams >= 2 into an overhead, and Eq. 7 is fitted per regime on
+ *   those samples in input order (small: size <= split_size).
+ *   Each fit is least squares on a shuffled 3:1 split: the caller passes the
+ *   shuffle as a permutation of the fit's points (perm_sum: one entry per distinct
+ *   size; perm_small / perm_big: one per overhead sample of that regime; a
+ *   regime without samples gets zero coefficients and its permutation is not
+ *   read); the first ceil(k/4) entries of a permutation are the test set.
+ *   report (may be NULL) receives 3 entries: sum model, small, big.
+ * Errors: WF_EINVAL for NULL pointers, invalid samples, a permutation that is not
+ * one, or too few / degenerate training points. */
+wf_status wf_stream_model_fit(const wf_stream_sample* samples, int64_t count, double split_size,
+                              const int64_t* perm_sum, const int64_t* perm_small, const int64_t* perm_big,
+                              wf_stream_model* out, wf_fit_report* report);
+/* Eq. 7: the modelled overhead of s streams at `size` (NaN for a NULL model or s < 1). */
+double wf_stream_model_overhead(const wf_stream_model* m, double size, int32_t s);
+/* Section 3's choice: among `ncand` candidate stream counts (NULL = 1, 2, 4, 8, 16,
+ * 32) the one whose gap (s-1)/s * sum_model(size) - overhead(size, s) (Eq. 6) is
+ * largest and positive; 1 when no gap is positive.  gaps (may be NULL) receives
+ * one gap per candidate. */
+wf_status wf_stream_model_choose(const wf_stream_model* m, double size, const int32_t* candidates, int32_t ncand,
+                                 int32_t* best, double* gaps);
+
 /* ----------------------------------------------------------------- errors */
 const char* wf_last_error(void);
 const char* wf_status_str(wf_status s);

@@ -69,6 +69,22 @@ class Result(ctypes.Structure):
                 ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
 
 
+class StreamSample(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_double), ("streams", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("t_str", ctypes.c_double), ("t_non_str", ctypes.c_double), ("sum", ctypes.c_double)]
+
+
+class StreamModel(ctypes.Structure):
+    _fields_ = [("sum_slope", ctypes.c_double), ("sum_intercept", ctypes.c_double),
+                ("split_size", ctypes.c_double), ("small", ctypes.c_double * 3), ("big", ctypes.c_double * 3)]
+
+
+class FitReport(ctypes.Structure):
+    _fields_ = [("r2_train", ctypes.c_double), ("r2_test", ctypes.c_double),
+                ("mse_train", ctypes.c_double), ("mse_test", ctypes.c_double),
+                ("n_train", ctypes.c_int64), ("n_test", ctypes.c_int64)]
+
+
 # Every symbol the C header declares, with its ctypes signature.
 _P = ctypes.c_void_p
 _SIGS = {
@@ -83,6 +99,14 @@ _SIGS = {
     "wf_release": (ctypes.c_int, [_P, ctypes.c_uint64]),
     "wf_server_destroy": (ctypes.c_int, [_P]),
     "wf_server_memory": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "wf_stream_model_fit": (ctypes.c_int, [ctypes.POINTER(StreamSample), ctypes.c_int64, ctypes.c_double,
+                                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(StreamModel),
+                                           ctypes.POINTER(FitReport)]),
+    "wf_stream_model_overhead": (ctypes.c_double, [ctypes.POINTER(StreamModel), ctypes.c_double, ctypes.c_int32]),
+    "wf_stream_model_choose": (ctypes.c_int, [ctypes.POINTER(StreamModel), ctypes.c_double,
+                                              ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "wf_last_error": (ctypes.c_char_p, []),
     "wf_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "wf_version": (ctypes.c_char_p, []),
@@ -370,3 +394,50 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------ stream-count model
+def stream_model_groups(samples, split_size):
+    """Point counts of the three fits wf_stream_model_fit makes from `samples`
+    ((size, streams, t_str, t_non_str, sum) tuples): distinct sizes, small-regime
+    overhead samples, big-regime overhead samples.  A caller needs them to draw
+    the shuffles it passes in."""
+    sizes = []
+    for s in samples:
+        if s[0] not in sizes:
+            sizes.append(s[0])
+    small = sum(1 for s in samples if s[1] >= 2 and s[0] <= split_size)
+    big = sum(1 for s in samples if s[1] >= 2 and s[0] > split_size)
+    return len(sizes), small, big
+
+
+def fit_stream_model(samples, split_size, perm_sum, perm_small, perm_big):
+    """Fit the model of Sections 2.3-2.4 (Eqs. 4, 5, 7) to (size, streams, t_str,
+    t_non_str, sum) samples with the given 3:1-split shuffles.  Returns
+    (StreamModel, [FitReport x 3]) for the sum, small and big fits."""
+    lib = load_library()
+    arr = (StreamSample * len(samples))()
+    for i, (size, s, t_str, t_non, sm) in enumerate(samples):
+        arr[i] = StreamSample(float(size), int(s), 0, float(t_str), float(t_non), float(sm))
+
+    def iarr(p):
+        a = (ctypes.c_int64 * max(len(p), 1))()
+        for i, v in enumerate(p):
+            a[i] = int(v)
+        return a
+
+    model = StreamModel()
+    rep = (FitReport * 3)()
+    _check(lib.wf_stream_model_fit(arr, len(samples), float(split_size), iarr(perm_sum), iarr(perm_small),
+                                   iarr(perm_big), ctypes.byref(model), rep))
+    return model, list(rep)
+
+
+def choose_streams(model, size, candidates=(1, 2, 4, 8, 16, 32)):
+    """Section 3's choice: (best stream count, [gap per candidate])."""
+    lib = load_library()
+    c = (ctypes.c_int32 * len(candidates))(*candidates)
+    g = (ctypes.c_double * len(candidates))()
+    best = ctypes.c_int32()
+    _check(lib.wf_stream_model_choose(ctypes.byref(model), float(size), c, len(candidates), ctypes.byref(best), g))
+    return best.value, list(g)

@@ -141,3 +141,9 @@ def fill_device(t, seed: int, row0: int = 0, n_cols: int | None = None, stream=N
     if rc != 0:
         raise RuntimeError(f"wfgen_fill failed with HIP error {rc}")
     return t
+
+
+def permutation(seed: int, n: int) -> np.ndarray:
+    """A seeded shuffle of range(n) (numpy PCG64): the random draw behind a
+    shuffled train/test split."""
+    return np.random.Generator(np.random.PCG64(seed)).permutation(n)
