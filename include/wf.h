@@ -121,6 +121,18 @@ wf_status wf_destroy(wf_ctx* ctx);
 /* Sweep one grid with one persistent kernel launch on `stream`. */
 wf_status wf_solve(wf_ctx* ctx, const wf_problem* p, void* stream);
 
+/* wf_solve with explicit tuning (NULL: as wf_solve): waves_per_wg picks bands of 64 or
+ * 128 rows (two compute waves chained through LDS), max_wgs caps the persistent
+ * workgroups; order and use_graph are ignored. */
+wf_status wf_solve_tuned(wf_ctx* ctx, const wf_problem* p, const wf_tuning* t, void* stream);
+
+/* The per-grid path: every problem swept by its own launch (as wf_solve), problem i
+ * on streams[i % nstreams].  Launches on different streams may run concurrently;
+ * up to 64 launches of a context are in flight before a launch waits for the
+ * oldest to finish.  The stream count is the parameter the paper's model chooses
+ * (wf_stream_model_choose). */
+wf_status wf_solve_each(wf_ctx* ctx, const wf_problem* ps, int64_t count, void* const* streams, int32_t nstreams);
+
 /* Sweep `count` independent grids of any sizes in one persistent launch on
  * `stream`; the bands of all grids are packed into one work list so the thin
  * first and last diagonals of one grid overlap the wide middle of another.
@@ -135,6 +147,12 @@ wf_status wf_solve(wf_ctx* ctx, const wf_problem* p, void* stream);
  * when the same batch shape is solved again. */
 wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t count, const wf_tuning* t, void* stream);
 
+/* Set the device watchdog of later launches on this context: a wait for a
+ * neighbouring band that makes no progress for `ms` milliseconds (0 .. 3600000)
+ * aborts the launch, which then drains and is reported as WF_ETIMEDOUT.  The
+ * default is 2000 ms (or WF_WATCHDOG_MS from the environment at wf_init). */
+wf_status wf_set_watchdog(wf_ctx* ctx, int64_t ms);
+
 /* Wait for all work this context has enqueued and return WF_ETIMEDOUT if the
  * device watchdog fired in any of it, WF_OK otherwise.  (wf_solve and
  * wf_solve_batched report such an error too, on the first call after the
@@ -148,20 +166,34 @@ typedef struct wf_server_opts {
   int64_t hbm_budget_bytes;  /* bytes of device memory the server may hold for requests (0 = 64 GiB) */
   int32_t max_inflight;      /* launches allowed in flight at once (0 = 4), each on its own stream */
   int32_t max_batch;         /* requests per launch at most (0 = 256) */
-  int32_t reserved[4];       /* must be 0 */
+  int32_t copy_streams;      /* streams that copy host inputs at admission, overlapping earlier launches
+                                (0 = copy on the launch stream just before the launch; at most 8) */
+  int32_t max_wait_skip_us;  /* a request that does not fit the budget yet may be overtaken by later,
+                                smaller ones until it has waited this long (0 = 20000 us) */
+  int64_t staging_bytes;     /* pinned staging for pageable host inputs when copy_streams > 0 (0 = 256 MiB) */
+  int32_t reserved[2];       /* must be 0 */
 } wf_server_opts;
 
-enum { WF_INPUT_DEVICE = 0, WF_INPUT_HOST = 1 };
+enum {
+  WF_INPUT_DEVICE = 0,       /* `input` is device memory, read in place */
+  WF_INPUT_HOST = 1,         /* `input` is pageable host memory, copied into a server-owned slot */
+  WF_INPUT_SEED = 2,         /* no `input`: cell (i, j) is output i*n + j of the SplitMix64 stream seeded
+                                with `seed` (float32: (x >> 40) * 2^-24; int32: x & 255), generated on
+                                the device into a server-owned slot */
+  WF_INPUT_HOST_PINNED = 3   /* `input` is pinned host memory (hipHostMalloc), copied by DMA without staging */
+};
 
 typedef struct wf_request {
   int64_t m, n;
   int32_t dtype, rule, mode;
-  int32_t input_kind;        /* WF_INPUT_DEVICE: `input` is a device pointer the caller keeps valid
-                                until wf_poll reports completion; WF_INPUT_HOST: host memory copied
-                                into a server-owned slot at admission (the caller may reuse it once
-                                wf_poll has reported completion) */
+  int32_t input_kind;        /* WF_INPUT_*.  Device inputs must stay valid and unchanged until wf_poll
+                                reports completion; host inputs may be reused once it has */
   const void* input;
-  int64_t ld_input;          /* elements, >= n */
+  int64_t ld_input;          /* elements, >= n (ignored for WF_INPUT_SEED) */
+  uint64_t seed;             /* WF_INPUT_SEED only */
+  void* ready_event;         /* WF_INPUT_DEVICE: a hipEvent_t recorded after the input was written (the
+                                launch waits for it on the device), or NULL when the input is already
+                                complete at wf_submit; the event must not be destroyed before completion */
 } wf_request;
 
 typedef struct wf_result {
@@ -190,6 +222,13 @@ wf_status wf_release(wf_server* s, uint64_t ticket);
 wf_status wf_server_destroy(wf_server* s);
 /* Bytes of device memory currently held for requests, and the peak so far. */
 wf_status wf_server_memory(wf_server* s, int64_t* in_use, int64_t* peak);
+
+/* Latency of one step of the walk's dependency chain on this device, in ns: one wave
+ * runs `steps` (16 .. 2^30) steps of N = the neighbour lane's H, H = c + min(N, NW, H)
+ * with nothing else on the compute unit (synchronous; allocates a few bytes).  The
+ * shortest possible sweep of an m x n grid by lanes that each own a row takes
+ * (m + n - 1) such steps: the sweep's latency floor. */
+wf_status wf_measure_step_ns(wf_ctx* ctx, int64_t steps, double* ns_per_step);
 
 /* ------------------------------------------ launch-concurrency (stream) model
  * The model of arXiv 2501.05938, Sections 2.3-2.4 (Eqs. 3-7) and the selection

@@ -53,13 +53,19 @@ class Tuning(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("max_batch", ctypes.c_int32), ("copy_streams", ctypes.c_int32),
+                ("max_wait_skip_us", ctypes.c_int32), ("staging_bytes", ctypes.c_int64),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+INPUT_DEVICE, INPUT_HOST, INPUT_SEED, INPUT_HOST_PINNED = 0, 1, 2, 3
 
 
 class Request(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64),
                 ("dtype", ctypes.c_int32), ("rule", ctypes.c_int32), ("mode", ctypes.c_int32),
-                ("input_kind", ctypes.c_int32), ("input", ctypes.c_void_p), ("ld_input", ctypes.c_int64)]
+                ("input_kind", ctypes.c_int32), ("input", ctypes.c_void_p), ("ld_input", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("ready_event", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
@@ -92,7 +98,11 @@ _SIGS = {
     "wf_destroy": (ctypes.c_int, [_P]),
     "wf_solve": (ctypes.c_int, [_P, ctypes.POINTER(Problem), _P]),
     "wf_solve_batched": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.c_int64, ctypes.POINTER(Tuning), _P]),
+    "wf_solve_tuned": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(Tuning), _P]),
+    "wf_solve_each": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.c_int64, ctypes.POINTER(_P), ctypes.c_int32]),
+    "wf_set_watchdog": (ctypes.c_int, [_P, ctypes.c_int64]),
     "wf_check": (ctypes.c_int, [_P]),
+    "wf_measure_step_ns": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     "wf_server_create": (ctypes.c_int, [_P, ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)]),
     "wf_submit": (ctypes.c_int, [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
     "wf_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(Result)]),
@@ -200,7 +210,7 @@ def make_problem(cost, out=None, rule="min", top=None, left=None, mode="full",
 
 
 def solve(cost, out=None, rule: str = "min", top=None, left=None, mode: str = "full", stream=None,
-          last_row=None, last_col=None, final_cell=None):
+          last_row=None, last_col=None, final_cell=None, waves_per_wg: int = 0, max_wgs: int = 0):
     """Sweep one grid on the GPU (asynchronous on `stream`, default: current stream).
 
     mode="full": returns H (m x n), written into `out` if given.
@@ -220,7 +230,13 @@ def solve(cost, out=None, rule: str = "min", top=None, left=None, mode: str = "f
         if final_cell is None:
             final_cell = torch.empty(1, dtype=cost.dtype, device=cost.device)
     p = make_problem(cost, out, rule, top, left, mode, last_row, last_col, final_cell)
-    _check(load_library().wf_solve(context(cost.device.index), ctypes.byref(p), _stream_ptr(stream)))
+    if waves_per_wg or max_wgs:
+        t = Tuning()
+        t.waves_per_wg, t.max_wgs = waves_per_wg, max_wgs
+        _check(load_library().wf_solve_tuned(context(cost.device.index), ctypes.byref(p), ctypes.byref(t),
+                                             _stream_ptr(stream)))
+    else:
+        _check(load_library().wf_solve(context(cost.device.index), ctypes.byref(p), _stream_ptr(stream)))
     if mode == "full":
         return out
     return last_row, last_col, final_cell
@@ -268,6 +284,32 @@ class BatchPlan:
         return self.outs
 
 
+class EachPlan:
+    """The per-grid path over a fixed list of grids: every grid swept by its own launch
+    (wf_solve_each), grid i on streams[i % len(streams)].  Arguments are marshalled
+    once, so run() measures the library's launches, not Python."""
+
+    def __init__(self, costs, outs=None, rule: str = "min"):
+        import torch
+        if outs is None:
+            outs = [torch.empty_like(c) for c in costs]
+        arr = (Problem * len(costs))()
+        for i, (c, o) in enumerate(zip(costs, outs)):
+            arr[i] = make_problem(c, o, rule)
+        self.costs, self.outs, self._arr = list(costs), outs, arr
+        self._device = costs[0].device.index if costs else None
+
+    def run(self, streams):
+        sp = (_P * len(streams))(*[s.cuda_stream for s in streams])
+        _check(load_library().wf_solve_each(context(self._device), self._arr, len(self.costs), sp, len(streams)))
+        return self.outs
+
+
+def set_watchdog(ms: int, device: int | None = None):
+    """Device watchdog of later launches on this thread's context (milliseconds)."""
+    _check(load_library().wf_set_watchdog(context(device), int(ms)))
+
+
 def solve_batched(costs, outs=None, rule: str = "min", mode: str = "full", stream=None,
                   waves_per_wg: int = 0, max_wgs: int = 0, order: int = 0, use_graph: int = 1):
     """Sweep many independent grids in one persistent launch.  Returns the list of outputs
@@ -302,25 +344,44 @@ class Server:
         srv.release(t)
     """
 
-    def __init__(self, budget_bytes: int = 0, max_inflight: int = 0, max_batch: int = 0, device: int | None = None):
+    def __init__(self, budget_bytes: int = 0, max_inflight: int = 0, max_batch: int = 0, device: int | None = None,
+                 copy_streams: int = 0, staging_bytes: int = 0, max_wait_skip_us: int = 0, ctx=None):
         lib = load_library()
         o = ServerOpts()
         o.hbm_budget_bytes, o.max_inflight, o.max_batch = budget_bytes, max_inflight, max_batch
+        o.copy_streams, o.staging_bytes, o.max_wait_skip_us = copy_streams, staging_bytes, max_wait_skip_us
         self._h = _P()
-        _check(lib.wf_server_create(context(device), ctypes.byref(o), ctypes.byref(self._h)))
+        _check(lib.wf_server_create(context(device) if ctx is None else ctx, ctypes.byref(o), ctypes.byref(self._h)))
         self._keep = {}
 
+    def _submit(self, r, keep):
+        t = ctypes.c_uint64()
+        _check(load_library().wf_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = keep
+        return t.value
+
     def submit(self, cost, rule: str = "min", mode: str = "full") -> int:
-        """Queue one grid; `cost` is a 2-D float32/int32 device tensor or a C-contiguous host
-        numpy array.  Returns the ticket."""
+        """Queue one grid; `cost` is a 2-D float32/int32 device tensor (the launch waits,
+        on the device, for the work already queued on the current stream, which may
+        still be writing it), a pinned CPU tensor (copied by DMA), or a C-contiguous host
+        numpy array / CPU tensor (copied through staging).  Returns the ticket."""
         import numpy as np
+        import torch
         r = Request()
-        if hasattr(cost, "is_cuda") and cost.is_cuda:
+        ev = None
+        if isinstance(cost, torch.Tensor) and cost.is_cuda:
             m, n = cost.shape
             r.dtype = DTYPES[_dtype_of(cost)]
-            r.input_kind, r.input, r.ld_input = 0, cost.data_ptr(), _ld(cost, n)
+            r.input_kind, r.input, r.ld_input = INPUT_DEVICE, cost.data_ptr(), _ld(cost, n)
+            ev = torch.cuda.Event()
+            ev.record(torch.cuda.current_stream(cost.device))
+            r.ready_event = ev.cuda_event
+        elif isinstance(cost, torch.Tensor) and cost.is_pinned():
+            m, n = cost.shape
+            r.dtype = DTYPES[_dtype_of(cost)]
+            r.input_kind, r.input, r.ld_input = INPUT_HOST_PINNED, cost.data_ptr(), _ld(cost, n)
         else:
-            a = np.ascontiguousarray(cost)
+            a = np.ascontiguousarray(cost.numpy() if isinstance(cost, torch.Tensor) else cost)
             if a.dtype == np.float32:
                 r.dtype = 0
             elif a.dtype == np.int32:
@@ -329,12 +390,18 @@ class Server:
                 raise TypeError("cost must be float32 or int32")
             m, n = a.shape
             cost = a
-            r.input_kind, r.input, r.ld_input = 1, a.ctypes.data, n
+            r.input_kind, r.input, r.ld_input = INPUT_HOST, a.ctypes.data, n
         r.m, r.n, r.rule, r.mode = m, n, RULES[rule], MODES[mode]
-        t = ctypes.c_uint64()
-        _check(load_library().wf_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
-        self._keep[t.value] = (cost, m, n, r.dtype, mode)
-        return t.value
+        return self._submit(r, (cost, m, n, r.dtype, mode, ev))
+
+    def submit_seeded(self, m: int, n: int, seed: int, dtype: str = "f32", rule: str = "min",
+                      mode: str = "full") -> int:
+        """Queue an m x n grid whose inputs the server generates on the device from `seed`
+        (SplitMix64, as wfgen.cells(seed, m, n, dtype))."""
+        r = Request()
+        r.m, r.n, r.dtype, r.rule, r.mode = m, n, DTYPES[dtype], RULES[rule], MODES[mode]
+        r.input_kind, r.seed = INPUT_SEED, seed & 0xFFFFFFFFFFFFFFFF
+        return self._submit(r, (None, m, n, r.dtype, mode, None))
 
     def poll(self, ticket: int):
         """None while pending; else a dict with torch views of the results and timestamps."""
@@ -344,7 +411,7 @@ class Server:
         if st == WF_PENDING:
             return None
         _check(st)
-        _, m, n, dt, mode = self._keep[ticket]
+        _, m, n, dt, mode, _ = self._keep[ticket]
         ts = "<f4" if dt == 0 else "<i4"
 
         def view(ptr, shape, strides=None):
@@ -441,3 +508,10 @@ def choose_streams(model, size, candidates=(1, 2, 4, 8, 16, 32)):
     best = ctypes.c_int32()
     _check(lib.wf_stream_model_choose(ctypes.byref(model), float(size), c, len(candidates), ctypes.byref(best), g))
     return best.value, list(g)
+
+
+def measure_step_ns(steps: int = 1 << 22, device: int | None = None) -> float:
+    """Latency of one step of the walk's dependency chain (ns), measured on the device."""
+    v = ctypes.c_double()
+    _check(load_library().wf_measure_step_ns(context(device), steps, ctypes.byref(v)))
+    return v.value

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["wf_kernel.hip", "wf_runtime.cpp", "wf_server.cpp", "wf_model.cpp"]
+SOURCES = ["wf_kernel.hip", "wf_seed.hip", "wf_probe.hip", "wf_runtime.cpp", "wf_server.cpp", "wf_model.cpp"]
 LIB = os.path.join(HERE, "libwf.so")
 ARCH = "gfx950"
 

@@ -1,6 +1,6 @@
 // wf_host.h -- host-side pieces shared by the runtime (wf_runtime.cpp) and the
 // serving front end (wf_server.cpp): the per-device context, launch slots,
-// argument checking and launch configuration.
+// batch plans, argument checking and launch configuration.
 #pragma once
 
 #include "../../include/wf.h"
@@ -9,13 +9,14 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <memory>
 #include <string>
 #include <utility>
 #include <vector>
 
 // A launch slot owns everything one in-flight launch mutates: control words,
-// handoff rows, descriptor table and work list.  Slots are reused round-robin
-// once their last launch has completed.
+// handoff rows, descriptor table and work list.  A slot is reused only once its
+// last launch has completed (its event has fired and its error word was read).
 struct Slot {
   uint32_t* ctl = nullptr;        // CTL_WORDS device words
   uint32_t* hand = nullptr;       // handoff rows (kept at the sentinel between launches)
@@ -28,24 +29,54 @@ struct Slot {
   uint32_t* host_err = nullptr;   // pinned copy of ctl[CTL_ERROR] after the launch
   hipEvent_t done = nullptr;      // recorded after the launch and the error copy
   bool pending = false;           // a launch was recorded and not yet checked
+  bool needs_rearm = false;       // an aborted launch left handoff rows written: refill before reuse
+  bool reserved = false;          // held by a cached batch plan
+  bool external = false;          // ctl/hand live in memory the slot does not own
 };
 
-struct GraphEntry {
-  hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
-  int slot = -1;
-  std::vector<wfk::GridDesc> descs;  // the descriptor table now in the slot's device copy
+// A batch whose work list, descriptor tables and (optionally) captured graphs are
+// kept for replay.  Two lanes, each with its own slot, let two replays be in flight.
+struct BatchPlanEntry {
+  uint64_t hash = 0;
+  std::vector<wf_problem> probs;          // the problem array last launched through this plan
+  std::vector<int64_t> shape;             // (m, n, mode) per problem: what the plan depends on
+  int W = 1, order = 1, nwg = 0, dtype = 0, rule = 0;
+  bool use_graph = false;
+  std::vector<int64_t> perm;              // problem index of descriptor k
+  std::vector<wfk::Item> items;
+  std::vector<size_t> hand_off;
+  size_t hand_total = 0;
+  struct Lane {
+    int slot = -1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<wfk::GridDesc> descs;     // the table now in the slot's device copy
+    wfk::GridDesc* staging = nullptr;     // pinned staging for table re-uploads
+    bool items_loaded = false;            // the work list is in the slot's device copy
+  };
+  Lane lanes[2];
+  uint64_t replays = 0;
+  uint64_t last_use = 0;
+};
+
+struct TuneEntry {
+  int W = 1, order = 1, wgs = 0;
+  double ms = 0;
 };
 
 struct wf_ctx {
   int device = 0;
   int num_cus = 256;
   uint64_t watchdog_ticks = 200000000ull;  // 2 s of the 100 MHz device wall clock
-  static constexpr int NSLOT = 8;
-  Slot slots[NSLOT];
-  int next_slot = 0;
-  std::map<std::string, GraphEntry> graphs;
-  std::map<std::string, std::pair<int, int>> tuned;  // batch shape signature -> (W, order)
+  uint32_t fault = 0;                      // test hook (WF_FAULT): band whose handoff the next launch drops, + 1
+  static constexpr int MAX_SLOTS = 64;     // launches in flight per context before a launch blocks
+  std::vector<std::unique_ptr<Slot>> slots;
+  size_t next_slot = 0;
+  static constexpr int MAX_PLANS = 8;
+  std::vector<std::unique_ptr<BatchPlanEntry>> plans;
+  uint64_t use_clock = 0;
+  std::map<std::string, TuneEntry> tuned;  // shape class -> configuration
+  std::string tune_file;                   // WF_TUNE_CACHE: where `tuned` persists (empty: memory only)
   wf_status sticky = WF_OK;                // device error seen, reported once
 };
 
@@ -57,7 +88,7 @@ wf_status fail(wf_status s, const std::string& msg);
 wf_status set_device(wf_ctx* ctx);
 // Validate one problem (idx >= 0 names it in the message).
 wf_status check_problem(const wf_problem* p, int64_t idx);
-// Compute waves per workgroup for a grid (or batch) whose tallest grid has m rows.
+// Compute waves per workgroup for a single grid with m rows.
 int choose_waves(int64_t m);
 // Resident workgroups per compute unit at W compute waves per workgroup.
 int wgs_per_cu(int W);
@@ -67,6 +98,9 @@ uint32_t sentinel_of(int dtype);
 wfk::GridDesc make_desc(const wf_problem* p, int W, uint32_t* hand);
 // Handoff-row elements a problem needs at W.
 size_t hand_elems(const wf_problem* p, int W);
+// Arguments of a launch over `nitems` work items with the context's watchdog and fault hook.
+// (Consumes the context's one-shot fault hook.)
+wfk::KArgs base_args(wf_ctx* ctx, uint32_t* ctl, int64_t nitems);
 
 }  // namespace wfh
 

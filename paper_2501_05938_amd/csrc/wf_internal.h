@@ -37,6 +37,7 @@ struct KArgs {
   uint64_t* trace;        // optional: TRACE_WORDS per (work item, compute wave), see below
   uint64_t* ctrace;       // optional: CTRACE_WORDS per (work item, compute wave, chunk), see below
   int64_t ctrace_nc;      // chunks per (work item, compute wave) in ctrace
+  uint32_t fault_band;    // test hook: band (of every grid) + 1 whose bottom row is never handed off; 0 = none
 };
 
 // Per (work item, compute wave) trace record, written when KArgs::trace is set:

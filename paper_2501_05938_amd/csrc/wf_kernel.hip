@@ -536,7 +536,8 @@ __device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLd
   const int G = (int)groups_for(n);
   const int gT = n >= 2 ? (int)((n - 2) / 4 + 1) : 0;
   const bool lds_consumer = (w + 1 < W && row0 + 64 < m);
-  const bool glob_consumer = (w == W - 1) && (band + 1 < g.nbands);
+  // (The fault hook drops one band's handoff: its consumer then waits until the watchdog fires.)
+  const bool glob_consumer = (w == W - 1) && (band + 1 < g.nbands) && a.fault_band != (uint32_t)band + 1u;
   const int64_t row = row0 + lane;
   if (a.trace && lane == 0) {
     L.tr_start = __builtin_readcyclecounter();
@@ -685,6 +686,15 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
     const int64_t room = span - 4 - max_rel;
     if (room >= 0) k_clean = (int)(room / 16 + 1 < NC ? room / 16 + 1 : NC);
   }
+  // With row padding (ld_cost > n), quads right of column n-1 would pick up the padding,
+  // which may hold any bit pattern (even the handoff sentinel, once it has gone through
+  // the cell rule).  From the first chunk where row 0's last quad reaches column n on,
+  // such quads are replaced by zeros (the fix-up path below).
+  const bool padded = g.ld_cost > B.n;
+  if (padded) {
+    const int k_pad = B.n >= 16 ? (int)((B.n - 16) / 16 + 1) : 0;  // first k with 16k + 15 >= n
+    if (k_clean > k_pad) k_clean = k_pad;
+  }
   uint32_t voff0[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) voff0[i] = (uint32_t)(ln.rel[i] * 4);  // used only for clean chunks
@@ -732,7 +742,8 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
       for (int i = 0; i < 4; ++i) {
         const int64_t col = 16 * k + 4 * (lane & 3) - ln.rho[i];
         const int64_t e = ln.rel[i] + 16 * k;
-        fix[i] = ln.real[i] && e + 4 > span && col <= B.n - 1 && col + 3 >= 0;
+        fix[i] = ln.real[i] && col + 3 >= 0 &&
+                 ((e + 4 > span && col <= B.n - 1) || (padded && col + 3 > B.n - 1));
         any |= fix[i];
       }
       if (__builtin_amdgcn_ballot_w64(any)) {
@@ -1046,6 +1057,34 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
 constexpr int storers_for(int W) { return W; }
 constexpr int waves_for(int W) { return 2 * W + storers_for(W) + 1; }
 
+// Wave index -> role.  A workgroup's waves are dealt over the four SIMDs of its compute
+// unit in turn, so waves i and i + 4 share a SIMD.  A compute wave's walk is one
+// dependent chain: a busy wave on the same SIMD lengthens every step, so the compute
+// waves get the quietest places: alone at W = 1; at W = 2 one alone and one beside the
+// feeder, while the loaders pair up and so do the storers.
+enum RoleKind { R_COMPUTE = 0, R_LOADER = 1, R_STORER = 2, R_FEEDER = 3 };
+struct Role {
+  int kind, strip;
+};
+template <int W>
+__device__ __forceinline__ Role role_of(int wave) {
+  if constexpr (W == 1) {
+    constexpr int kinds[4] = {R_COMPUTE, R_LOADER, R_STORER, R_FEEDER};
+    return Role{kinds[wave & 3], 0};
+  } else {
+    static_assert(W == 2, "roles are laid out for one or two compute waves");
+    switch (wave) {
+      case 0: return Role{R_COMPUTE, 1};
+      case 1: return Role{R_LOADER, 0};
+      case 2: return Role{R_STORER, 0};
+      case 3: return Role{R_COMPUTE, 0};
+      case 4: return Role{R_FEEDER, 0};
+      case 5: return Role{R_LOADER, 1};
+      default: return Role{R_STORER, 1};
+    }
+  }
+}
+
 // Two waves per SIMD at most (the LDS rings allow two workgroups of one compute wave per
 // compute unit, or one of two), so up to 256 VGPRs each.  TR: the launch records
 // traces; without it every trace branch is compiled out of the walk.
@@ -1063,6 +1102,7 @@ void wf_sweep_kernel(KArgs a_in) {
   __shared__ uint32_t s_item;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
+  const Role role = role_of<W>(__builtin_amdgcn_readfirstlane(wave));
   for (;;) {
     if (threadIdx.x == 0) {
       uint32_t t = atomicAdd(&a.ctl[CTL_TICKET], 1u);
@@ -1070,8 +1110,8 @@ void wf_sweep_kernel(KArgs a_in) {
       s_item = t;
     }
     // Re-arm this workgroup's LDS state for the next band.
-    if (wave < W) {
-      WaveLds& L = lds[wave];
+    if (role.kind == R_COMPUTE) {
+      WaveLds& L = lds[role.strip];
       const uint32_t SENT = Num<T>::SENT;
       for (int i = lane; i < RING_T; i += 64) L.tring[i] = SENT;
       if (lane == 0) {
@@ -1101,18 +1141,18 @@ void wf_sweep_kernel(KArgs a_in) {
       gd = a.g0;
       band = (int)t;
     }
-    if (wave < W) {
-      uint64_t* crec = a.ctrace ? a.ctrace + ((int64_t)t * W + wave) * a.ctrace_nc * CTRACE_WORDS : nullptr;
-      compute_band<T, RULE, W>(gd, band, lds, wave, lane, a, crec);
+    if (role.kind == R_COMPUTE) {
+      uint64_t* crec = a.ctrace ? a.ctrace + ((int64_t)t * W + role.strip) * a.ctrace_nc * CTRACE_WORDS : nullptr;
+      compute_band<T, RULE, W>(gd, band, lds, role.strip, lane, a, crec);
     }
-    else if (wave < 2 * W) loader_band<W>(gd, band, lds, wave - W, lane, a, t);
-    else if (wave < 2 * W + storers_for(W)) storer_band<T, W>(gd, band, lds, wave - 2 * W, lane, a, t);
+    else if (role.kind == R_LOADER) loader_band<W>(gd, band, lds, role.strip, lane, a, t);
+    else if (role.kind == R_STORER) storer_band<T, W>(gd, band, lds, role.strip, lane, a, t);
     else feeder_band<T, RULE, W>(gd, band, lds, lane, a);
     __syncthreads();
-    if (a.trace && wave < W && lane == 0) {
-      const WaveLds& L = lds[wave];
-      uint64_t* r = a.trace + ((uint64_t)t * W + wave) * TRACE_WORDS;
-      r[0] = ((uint64_t)(a.grids ? a.items[t].grid : 0) << 32) | ((uint64_t)band << 8) | (uint64_t)wave;
+    if (a.trace && role.kind == R_COMPUTE && lane == 0) {
+      const WaveLds& L = lds[role.strip];
+      uint64_t* r = a.trace + ((uint64_t)t * W + role.strip) * TRACE_WORDS;
+      r[0] = ((uint64_t)(a.grids ? a.items[t].grid : 0) << 32) | ((uint64_t)band << 8) | (uint64_t)role.strip;
       r[1] = L.tr_start;
       r[2] = L.tr_first;
       r[3] = L.tr_end;

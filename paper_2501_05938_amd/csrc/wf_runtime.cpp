@@ -1,19 +1,20 @@
 // wf_runtime.cpp -- the C ABI of libwf (include/wf.h): argument checking,
 // per-context workspace, launch configuration, batched work lists with hipGraph
-// replay, and error reporting.
+// replay, the autotuner and its persistent cache, and error reporting.
 #include "../../include/wf.h"
 #include "wf_internal.h"
 #include "wf_host.h"
 
 #include <algorithm>
-#include <atomic>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <memory>
-#include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -46,7 +47,7 @@ extern "C" const char* wf_status_str(wf_status s) {
   }
 }
 
-extern "C" const char* wf_version(void) { return "libwf 0.1 (gfx950)"; }
+extern "C" const char* wf_version(void) { return "libwf 0.2 (gfx950)"; }
 
 wf_status wfh::set_device(wf_ctx* ctx) {
   int cur = -1;
@@ -55,60 +56,99 @@ wf_status wfh::set_device(wf_ctx* ctx) {
   return WF_OK;
 }
 
-// Reads the device status of a finished slot; re-arms its handoff rows after an abort.
-static wf_status harvest(wf_ctx* ctx, Slot& s, hipStream_t stream, bool wait) {
+// ------------------------------------------------------------------ slots
+// Reads the device status of a slot's last launch.  wait: block until it is done.
+// After a watchdog abort the slot is marked for re-arming; the refill happens on the
+// stream of the slot's next launch (ensure_hand), so it is ordered before that launch.
+static wf_status harvest(Slot& s, bool wait) {
   if (!s.pending) return WF_OK;
   hipError_t q = wait ? hipEventSynchronize(s.done) : hipEventQuery(s.done);
   if (q == hipErrorNotReady) return WF_PENDING;
-  if (q != hipSuccess) return fail(WF_EHIP, std::string("launch failed: ") + hipGetErrorString(q));
   s.pending = false;
+  if (q != hipSuccess) {
+    s.needs_rearm = true;
+    return fail(WF_EHIP, std::string("launch failed: ") + hipGetErrorString(q));
+  }
   if (*s.host_err != DEV_OK) {
     *s.host_err = DEV_OK;
-    if (s.hand && s.hand_cap) {
-      hipError_t e = launch_fill_u32(s.hand, s.hand_sent, (int64_t)s.hand_cap, stream);
-      if (e != hipSuccess) return fail(WF_EHIP, std::string("re-arm: ") + hipGetErrorString(e));
-    }
+    s.needs_rearm = true;
     return fail(WF_ETIMEDOUT, "device watchdog fired: a wait for a neighbouring band exceeded the limit "
                               "(NaN or reserved-value inputs, or an oversubscribed device)");
   }
   return WF_OK;
 }
 
-static wf_status acquire_slot(wf_ctx* ctx, hipStream_t stream, Slot** out, int* index) {
-  const int i = ctx->next_slot;
-  ctx->next_slot = (ctx->next_slot + 1) % wf_ctx::NSLOT;
-  Slot& s = ctx->slots[i];
-  wf_status st = harvest(ctx, s, stream, true);
-  if (st == WF_ETIMEDOUT) ctx->sticky = WF_ETIMEDOUT;
-  else if (st != WF_OK) return st;
-  if (!s.ctl) {
-    WF_HIP(hipMalloc(&s.ctl, CTL_WORDS * sizeof(uint32_t)));
-    WF_HIP(hipHostMalloc(&s.host_err, sizeof(uint32_t), hipHostMallocDefault));
-    *s.host_err = 0;
-    WF_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+static wf_status note(wf_ctx* ctx, wf_status st) {
+  if (st == WF_ETIMEDOUT || st == WF_EHIP) {
+    if (ctx->sticky == WF_OK) ctx->sticky = st;
+    return WF_OK;
   }
-  *out = &s;
-  if (index) *index = i;
+  return st;
+}
+
+static wf_status new_slot(wf_ctx* ctx, Slot** out) {
+  std::unique_ptr<Slot> s(new Slot);
+  if (hipMalloc(&s->ctl, CTL_WORDS * sizeof(uint32_t)) != hipSuccess) return fail(WF_ENOMEM, "cannot allocate a launch slot");
+  WF_HIP(hipHostMalloc(&s->host_err, sizeof(uint32_t), hipHostMallocDefault));
+  *s->host_err = 0;
+  WF_HIP(hipEventCreateWithFlags(&s->done, hipEventDisableTiming));
+  ctx->slots.push_back(std::move(s));
+  *out = ctx->slots.back().get();
   return WF_OK;
 }
 
+// A free slot: the first unreserved slot whose last launch has finished, else a new
+// one while the pool is below MAX_SLOTS, else the oldest unreserved slot after
+// waiting for it.  Launches therefore never wait on one another's completion until
+// MAX_SLOTS of them are in flight.
+static wf_status acquire_slot(wf_ctx* ctx, Slot** out) {
+  const size_t n = ctx->slots.size();
+  for (size_t k = 0; k < n; ++k) {
+    const size_t i = (ctx->next_slot + k) % n;
+    Slot& s = *ctx->slots[i];
+    if (s.reserved) continue;
+    wf_status st = harvest(s, false);
+    if (st == WF_PENDING) continue;
+    st = note(ctx, st);
+    if (st != WF_OK) return st;
+    ctx->next_slot = (i + 1) % n;
+    *out = &s;
+    return WF_OK;
+  }
+  if ((int)n < wf_ctx::MAX_SLOTS) return new_slot(ctx, out);
+  for (size_t k = 0; k < n; ++k) {
+    const size_t i = (ctx->next_slot + k) % n;
+    Slot& s = *ctx->slots[i];
+    if (s.reserved) continue;
+    wf_status st = note(ctx, harvest(s, true));
+    if (st != WF_OK) return st;
+    ctx->next_slot = (i + 1) % n;
+    *out = &s;
+    return WF_OK;
+  }
+  return fail(WF_ENOMEM, "every launch slot is held by a cached batch plan");
+}
+
+// Handoff rows of at least `need` elements armed with `sent`, on `stream`.
 static wf_status ensure_hand(Slot& s, size_t need, uint32_t sent, hipStream_t stream) {
   if (need == 0) need = 64;
   if (s.hand_cap < need) {
+    if (s.external) return fail(WF_E2BIG, "the problem needs more handoff rows than the fixed workspace holds");
+    const size_t cap = std::max(need, s.hand_cap * 2);
     if (s.hand) WF_HIP(hipFree(s.hand));
     s.hand = nullptr;
     s.hand_cap = 0;
-    size_t cap = std::max(need, s.hand_cap * 2);
     if (hipMalloc(&s.hand, cap * sizeof(uint32_t)) != hipSuccess) {
       s.hand = nullptr;
       return fail(WF_ENOMEM, "cannot allocate handoff rows");
     }
     s.hand_cap = cap;
-    s.hand_sent = sent;
-    WF_HIP(launch_fill_u32(s.hand, sent, (int64_t)cap, stream));
-  } else if (s.hand_sent != sent) {
-    s.hand_sent = sent;
+    s.needs_rearm = true;
+  }
+  if (s.hand_sent != sent || s.needs_rearm) {
     WF_HIP(launch_fill_u32(s.hand, sent, (int64_t)s.hand_cap, stream));
+    s.hand_sent = sent;
+    s.needs_rearm = false;
   }
   return WF_OK;
 }
@@ -119,12 +159,19 @@ static wf_status ensure_buf(T** p, size_t* cap, size_t need) {
   if (*p) WF_HIP(hipFree(*p));
   *p = nullptr;
   *cap = 0;
-  size_t c = std::max<size_t>(need, 64);
+  const size_t c = std::max<size_t>(need, 64);
   if (hipMalloc(p, c * sizeof(T)) != hipSuccess) {
     *p = nullptr;
     return fail(WF_ENOMEM, "cannot allocate descriptor table");
   }
   *cap = c;
+  return WF_OK;
+}
+
+static wf_status finish_launch(Slot& s, hipStream_t stream) {
+  WF_HIP(hipMemcpyAsync(s.host_err, s.ctl + CTL_ERROR, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+  WF_HIP(hipEventRecord(s.done, stream));
+  s.pending = true;
   return WF_OK;
 }
 
@@ -156,23 +203,32 @@ wf_status wfh::check_problem(const wf_problem* p, int64_t idx) {
   return WF_OK;
 }
 
+static wf_status check_tuning(const wf_tuning& t) {
+  for (int i = 0; i < 4; ++i)
+    if (t.reserved[i] != 0) return fail(WF_EINVAL, "wf_tuning.reserved must be 0");
+  if (t.waves_per_wg < 0 || t.waves_per_wg > 2) return fail(WF_EINVAL, "waves_per_wg must be 0, 1 or 2");
+  if (t.max_wgs < 0 || t.order < 0 || t.order > 2 || t.use_graph < -1 || t.use_graph > 1)
+    return fail(WF_EINVAL, "bad tuning value");
+  return WF_OK;
+}
+
 // ------------------------------------------------------------ configuration
 int wfh::choose_waves(int64_t m) {
-  // Bands of 64*W rows.  A workgroup's W strips share one compute unit's memory
-  // pipeline (each strip has its own loader and storer), and that sharing costs more
-  // than the LDS handoff between them saves: one strip per workgroup, spread over the
-  // compute units, is fastest for a single grid.
+  // Bands of 64*W rows.  One strip per workgroup, spread over the compute units, is
+  // fastest for a single grid (compute waves sharing a compute unit slow each other
+  // more than the cheaper LDS handoff between them saves).
   (void)m;
   return 1;
 }
 
-// The LDS rings of one compute wave take about 65 KB of a compute unit's 160 KB.
+// The LDS rings of one compute wave take about 66 KB of a compute unit's 160 KB.
 int wfh::wgs_per_cu(int W) { return W >= 2 ? 1 : 2; }
 
 uint32_t wfh::sentinel_of(int dtype) { return dtype == WF_F32 ? SENT_F32 : SENT_I32; }
 
 GridDesc wfh::make_desc(const wf_problem* p, int W, uint32_t* hand) {
   GridDesc d;
+  std::memset(&d, 0, sizeof d);
   d.cost = p->cost;
   d.out = p->mode == WF_MODE_FULL ? p->out : nullptr;
   d.top = p->top;
@@ -196,11 +252,83 @@ size_t wfh::hand_elems(const wf_problem* p, int W) {
   return nb > 1 ? (size_t)(nb - 1) * (size_t)hand_ld_for(p->n) : 0;
 }
 
-static wf_status finish_launch(Slot& s, hipStream_t stream) {
-  WF_HIP(hipMemcpyAsync(s.host_err, s.ctl + CTL_ERROR, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
-  WF_HIP(hipEventRecord(s.done, stream));
-  s.pending = true;
-  return WF_OK;
+KArgs wfh::base_args(wf_ctx* ctx, uint32_t* ctl, int64_t nitems) {
+  KArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.nitems = nitems;
+  a.ctl = ctl;
+  a.watchdog_ticks = ctx->watchdog_ticks;
+  a.fault_band = ctx->fault;  // the fault hook fires on one launch only
+  ctx->fault = 0;
+  return a;
+}
+
+// ------------------------------------------------------------ tuning cache
+// WF_TUNE_CACHE names a JSON file holding the autotuner's choices per shape class:
+//   {"version": 1, "entries": [{"class": "...", "W": 1, "order": 2, "wgs": 512, "ms": 3.8}, ...]}
+static void load_tune_cache(wf_ctx* ctx) {
+  std::ifstream f(ctx->tune_file);
+  if (!f) return;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string t = ss.str();
+  size_t at = 0;
+  auto field = [&](size_t from, const char* key, size_t end, std::string* sval, double* nval) -> bool {
+    const std::string k = std::string("\"") + key + "\"";
+    size_t p = t.find(k, from);
+    if (p == std::string::npos || p >= end) return false;
+    p = t.find(':', p + k.size());
+    if (p == std::string::npos || p >= end) return false;
+    ++p;
+    while (p < end && (t[p] == ' ' || t[p] == '\t' || t[p] == '\n')) ++p;
+    if (sval) {
+      if (t[p] != '"') return false;
+      const size_t q = t.find('"', p + 1);
+      if (q == std::string::npos || q > end) return false;
+      *sval = t.substr(p + 1, q - p - 1);
+      return true;
+    }
+    char* e = nullptr;
+    *nval = std::strtod(t.c_str() + p, &e);
+    return e != t.c_str() + p;
+  };
+  while ((at = t.find('{', at + 1)) != std::string::npos) {
+    const size_t end = t.find('}', at);
+    if (end == std::string::npos) break;
+    std::string cls;
+    double W = 0, order = 0, wgs = 0, ms = 0;
+    if (field(at, "class", end, &cls, nullptr) && field(at, "W", end, nullptr, &W) &&
+        field(at, "order", end, nullptr, &order) && field(at, "wgs", end, nullptr, &wgs)) {
+      field(at, "ms", end, nullptr, &ms);
+      if ((W == 1 || W == 2) && (order == 1 || order == 2) && wgs >= 0) {
+        TuneEntry e;
+        e.W = (int)W;
+        e.order = (int)order;
+        e.wgs = (int)wgs;
+        e.ms = ms;
+        ctx->tuned[cls] = e;
+      }
+    }
+    at = end;
+  }
+}
+
+static void save_tune_cache(const wf_ctx* ctx) {
+  if (ctx->tune_file.empty()) return;
+  const std::string tmp = ctx->tune_file + ".tmp";
+  {
+    std::ofstream f(tmp);
+    if (!f) return;
+    f << "{\"version\": 1, \"entries\": [";
+    bool first = true;
+    for (const auto& kv : ctx->tuned) {
+      f << (first ? "\n" : ",\n") << "  {\"class\": \"" << kv.first << "\", \"W\": " << kv.second.W
+        << ", \"order\": " << kv.second.order << ", \"wgs\": " << kv.second.wgs << ", \"ms\": " << kv.second.ms << "}";
+      first = false;
+    }
+    f << "\n]}\n";
+  }
+  std::rename(tmp.c_str(), ctx->tune_file.c_str());
 }
 
 // ------------------------------------------------------------------ public
@@ -221,21 +349,44 @@ extern "C" wf_status wf_init(int device, wf_ctx** out) {
     long ms = std::atol(w);
     if (ms > 0) ctx->watchdog_ticks = (uint64_t)ms * 100000ull;
   }
+  if (const char* f = std::getenv("WF_FAULT")) {
+    // Test hook, drop_hand:<band>: in the context's first launch the given band (of every
+    // grid) never hands its bottom row on, so the band below waits until the watchdog
+    // fires and the launch drains.
+    if (std::strncmp(f, "drop_hand:", 10) == 0) ctx->fault = (uint32_t)std::atol(f + 10) + 1u;
+  }
+  if (const char* f = std::getenv("WF_TUNE_CACHE")) {
+    ctx->tune_file = f;
+    load_tune_cache(ctx.get());
+  }
   wf_status st = set_device(ctx.get());
   if (st != WF_OK) return st;
   *out = ctx.release();
   return WF_OK;
 }
 
+static void drop_plan(BatchPlanEntry& e, wf_ctx* ctx) {
+  for (auto& L : e.lanes) {
+    if (L.slot >= 0) {
+      Slot& s = *ctx->slots[(size_t)L.slot];
+      note(ctx, harvest(s, true));
+      s.reserved = false;
+    }
+    if (L.exec) hipGraphExecDestroy(L.exec);
+    if (L.graph) hipGraphDestroy(L.graph);
+    if (L.staging) hipHostFree(L.staging);
+    L = BatchPlanEntry::Lane();
+  }
+}
+
 extern "C" wf_status wf_destroy(wf_ctx* ctx) {
   if (!ctx) return WF_OK;
   set_device(ctx);
   hipDeviceSynchronize();
-  for (auto& kv : ctx->graphs) {
-    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
-    if (kv.second.graph) hipGraphDestroy(kv.second.graph);
-  }
-  for (auto& s : ctx->slots) {
+  for (auto& e : ctx->plans) drop_plan(*e, ctx);
+  for (auto& sp : ctx->slots) {
+    Slot& s = *sp;
+    if (s.external) continue;
     if (s.ctl) hipFree(s.ctl);
     if (s.hand) hipFree(s.hand);
     if (s.grids) hipFree(s.grids);
@@ -247,6 +398,13 @@ extern "C" wf_status wf_destroy(wf_ctx* ctx) {
   return WF_OK;
 }
 
+extern "C" wf_status wf_set_watchdog(wf_ctx* ctx, int64_t ms) {
+  if (!ctx) return fail(WF_EINVAL, "ctx is NULL");
+  if (ms < 0 || ms > 3600 * 1000) return fail(WF_EINVAL, "watchdog must be 0 .. 3600000 ms");
+  ctx->watchdog_ticks = (uint64_t)ms * 100000ull;
+  return WF_OK;
+}
+
 // Wait for every launch of the context and report a device error, if any.
 extern "C" wf_status wf_check(wf_ctx* ctx) {
   if (!ctx) return fail(WF_EINVAL, "ctx is NULL");
@@ -255,7 +413,7 @@ extern "C" wf_status wf_check(wf_ctx* ctx) {
   wf_status res = ctx->sticky;
   ctx->sticky = WF_OK;
   for (auto& s : ctx->slots) {
-    wf_status r = harvest(ctx, s, nullptr, true);
+    wf_status r = harvest(*s, true);
     if (r != WF_OK && res == WF_OK) res = r;
   }
   if (res == WF_ETIMEDOUT) return fail(WF_ETIMEDOUT, "device watchdog fired");
@@ -265,44 +423,31 @@ extern "C" wf_status wf_check(wf_ctx* ctx) {
 static wf_status report_sticky(wf_ctx* ctx) {
   // Non-blocking look at finished launches; report a device error once.
   for (auto& s : ctx->slots) {
-    wf_status r = harvest(ctx, s, nullptr, false);
-    if (r == WF_ETIMEDOUT) ctx->sticky = WF_ETIMEDOUT;
+    wf_status r = harvest(*s, false);
+    if (r != WF_PENDING) note(ctx, r);
   }
   if (ctx->sticky != WF_OK) {
     wf_status s = ctx->sticky;
     ctx->sticky = WF_OK;
-    return fail(s, "a previous launch on this context timed out");
+    return fail(s, s == WF_ETIMEDOUT ? "a previous launch on this context timed out"
+                                     : "a previous launch on this context failed");
   }
   return WF_OK;
 }
 
-extern "C" wf_status wf_solve(wf_ctx* ctx, const wf_problem* p, void* stream_) {
-  if (!ctx) return fail(WF_EINVAL, "ctx is NULL");
-  wf_status st = check_problem(p, -1);
-  if (st != WF_OK) return st;
-  st = set_device(ctx);
-  if (st != WF_OK) return st;
-  st = report_sticky(ctx);
-  if (st != WF_OK) return st;
-  if (p->m == 0 || p->n == 0) return WF_OK;
-  hipStream_t stream = (hipStream_t)stream_;
-  const int W = choose_waves(p->m);
+// One grid, one launch, at W compute waves per workgroup.
+static wf_status solve_one(wf_ctx* ctx, const wf_problem* p, int W, int max_wgs, hipStream_t stream) {
   Slot* s = nullptr;
-  st = acquire_slot(ctx, stream, &s, nullptr);
+  wf_status st = acquire_slot(ctx, &s);
   if (st != WF_OK) return st;
-  const uint32_t sent = sentinel_of(p->dtype);
-  st = ensure_hand(*s, hand_elems(p, W), sent, stream);
+  st = ensure_hand(*s, hand_elems(p, W), sentinel_of(p->dtype), stream);
   if (st != WF_OK) return st;
-  KArgs a;
-  std::memset(&a, 0, sizeof a);
+  KArgs a = base_args(ctx, s->ctl, 0);
   a.g0 = make_desc(p, W, s->hand);
-  a.grids = nullptr;
-  a.items = nullptr;
   a.nitems = a.g0.nbands;
-  a.ctl = s->ctl;
-  a.watchdog_ticks = ctx->watchdog_ticks;
   const int resident = ctx->num_cus * wgs_per_cu(W);
-  const int nwg = (int)std::min<int64_t>(a.nitems, resident);
+  int nwg = (int)std::min<int64_t>(a.nitems, resident);
+  if (max_wgs > 0) nwg = std::min(nwg, max_wgs);
   // Optional trace (profiling hook): WF_TRACE_FILE=<path> makes wf_solve synchronous
   // and writes TRACE_WORDS uint64 per (band, compute wave) to <path>.
   const char* trace_file = std::getenv("WF_TRACE_FILE");
@@ -346,199 +491,318 @@ extern "C" wf_status wf_solve(wf_ctx* ctx, const wf_problem* p, void* stream_) {
   return finish_launch(*s, stream);
 }
 
-// Batched: one persistent launch over the bands of all grids.
-static std::string batch_key(const wf_problem* ps, int64_t count, int W, int nwg, int order) {
-  std::string k;
-  k.reserve(32 + 24 * (size_t)count);
-  char buf[96];
-  snprintf(buf, sizeof buf, "%lld/%d/%d/%d/%d/%d|", (long long)count, ps[0].dtype, ps[0].rule, W, nwg, order);
-  k += buf;
-  for (int64_t i = 0; i < count; ++i) {
-    snprintf(buf, sizeof buf, "%lld,%lld,%d;", (long long)ps[i].m, (long long)ps[i].n, ps[i].mode);
-    k += buf;
-  }
-  return k;
+static wf_status solve_entry(wf_ctx* ctx, const wf_problem* p, const wf_tuning* t, void* stream_) {
+  if (!ctx) return fail(WF_EINVAL, "ctx is NULL");
+  wf_status st = check_problem(p, -1);
+  if (st != WF_OK) return st;
+  wf_tuning tun;
+  std::memset(&tun, 0, sizeof tun);
+  if (t) tun = *t;
+  st = check_tuning(tun);
+  if (st != WF_OK) return st;
+  st = set_device(ctx);
+  if (st != WF_OK) return st;
+  st = report_sticky(ctx);
+  if (st != WF_OK) return st;
+  if (p->m == 0 || p->n == 0) return WF_OK;
+  const int W = tun.waves_per_wg ? tun.waves_per_wg : choose_waves(p->m);
+  return solve_one(ctx, p, W, tun.max_wgs, (hipStream_t)stream_);
 }
 
-// One batched launch at a fixed configuration (arguments already checked).
-static wf_status batched_run(wf_ctx* ctx, const wf_problem* ps, int64_t count, int W, int order, int max_wgs,
-                             bool use_graph, hipStream_t stream) {
-  wf_status st = WF_OK;
-  // Grids in work order: largest first so the long critical paths start early.
-  std::vector<int64_t> perm;
-  perm.reserve((size_t)count);
+extern "C" wf_status wf_solve(wf_ctx* ctx, const wf_problem* p, void* stream) {
+  return solve_entry(ctx, p, nullptr, stream);
+}
+
+extern "C" wf_status wf_solve_tuned(wf_ctx* ctx, const wf_problem* p, const wf_tuning* t, void* stream) {
+  return solve_entry(ctx, p, t, stream);
+}
+
+extern "C" wf_status wf_solve_each(wf_ctx* ctx, const wf_problem* ps, int64_t count, void* const* streams,
+                                   int32_t nstreams) {
+  if (!ctx) return fail(WF_EINVAL, "ctx is NULL");
+  if (count < 0 || (count > 0 && !ps)) return fail(WF_EINVAL, "bad problem array");
+  if (nstreams < 1 || !streams) return fail(WF_EINVAL, "need at least one stream");
+  for (int64_t i = 0; i < count; ++i) {
+    wf_status st = check_problem(&ps[i], i);
+    if (st != WF_OK) return st;
+  }
+  wf_status st = set_device(ctx);
+  if (st != WF_OK) return st;
+  st = report_sticky(ctx);
+  if (st != WF_OK) return st;
+  for (int64_t i = 0; i < count; ++i) {
+    if (ps[i].m == 0 || ps[i].n == 0) continue;
+    st = solve_one(ctx, &ps[i], choose_waves(ps[i].m), 0, (hipStream_t)streams[i % nstreams]);
+    if (st != WF_OK) return st;
+  }
+  return WF_OK;
+}
+
+// ----------------------------------------------------------------- batched
+static uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// Grids in work order (largest first, so long critical paths start early) and the
+// (grid, band) work list: grid-major (order 1) or band-interleaved (order 2).
+static void build_work(const wf_problem* ps, int64_t count, int W, int order, std::vector<int64_t>& perm,
+                       std::vector<Item>& items, std::vector<size_t>& hand_off, size_t& hand_total) {
+  perm.clear();
+  items.clear();
   for (int64_t i = 0; i < count; ++i)
     if (ps[i].m > 0 && ps[i].n > 0) perm.push_back(i);
-  if (perm.empty()) return WF_OK;
-  std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) {
-    return ps[a].m * ps[a].n > ps[b].m * ps[b].n;
-  });
-  std::vector<GridDesc> descs(perm.size());
-  std::vector<Item> items;
-  size_t hand_total = 0;
-  std::vector<size_t> hand_off(perm.size());
+  std::stable_sort(perm.begin(), perm.end(),
+                   [&](int64_t a, int64_t b) { return ps[a].m * ps[a].n > ps[b].m * ps[b].n; });
+  hand_off.resize(perm.size());
+  hand_total = 0;
+  std::vector<int32_t> nb(perm.size());
+  int64_t max_bands = 0;
   for (size_t gi = 0; gi < perm.size(); ++gi) {
     hand_off[gi] = hand_total;
     hand_total += hand_elems(&ps[perm[gi]], W);
-  }
-  int64_t max_bands = 0;
-  for (size_t gi = 0; gi < perm.size(); ++gi) {
-    descs[gi] = make_desc(&ps[perm[gi]], W, nullptr);
-    max_bands = std::max<int64_t>(max_bands, descs[gi].nbands);
+    nb[gi] = (int32_t)((ps[perm[gi]].m + 64 * W - 1) / (64 * W));
+    max_bands = std::max<int64_t>(max_bands, nb[gi]);
   }
   if (order == 2) {
-    // Interleaved: band b of every grid before band b+1 of any grid.
     for (int64_t b = 0; b < max_bands; ++b)
       for (size_t gi = 0; gi < perm.size(); ++gi)
-        if (b < descs[gi].nbands) items.push_back(Item{(uint32_t)gi, (uint32_t)b});
+        if (b < nb[gi]) items.push_back(Item{(uint32_t)gi, (uint32_t)b});
   } else {
     for (size_t gi = 0; gi < perm.size(); ++gi)
-      for (int b = 0; b < descs[gi].nbands; ++b) items.push_back(Item{(uint32_t)gi, (uint32_t)b});
+      for (int32_t b = 0; b < nb[gi]; ++b) items.push_back(Item{(uint32_t)gi, (uint32_t)b});
   }
-  const int resident = ctx->num_cus * wgs_per_cu(W);
-  int nwg = (int)std::min<int64_t>((int64_t)items.size(), resident);
+}
+
+static int batch_wgs(const wf_ctx* ctx, int W, int64_t nitems, int max_wgs) {
+  int nwg = (int)std::min<int64_t>(nitems, (int64_t)ctx->num_cus * wgs_per_cu(W));
   if (max_wgs > 0) nwg = std::min(nwg, max_wgs);
+  return std::max(nwg, 1);
+}
 
-  const std::string key = use_graph ? batch_key(ps, count, W, nwg, order) : std::string();
+// A batched launch that is not kept for replay (autotuning trials, plain launches).
+static wf_status batched_once(wf_ctx* ctx, const wf_problem* ps, int64_t count, int W, int order, int max_wgs,
+                              hipStream_t stream) {
+  std::vector<int64_t> perm;
+  std::vector<Item> items;
+  std::vector<size_t> hand_off;
+  size_t hand_total = 0;
+  build_work(ps, count, W, order, perm, items, hand_off, hand_total);
+  if (items.empty()) return WF_OK;
   Slot* s = nullptr;
-  int slot_index = -1;
-  GraphEntry* ge = nullptr;
-  if (use_graph) {
-    auto it = ctx->graphs.find(key);
-    if (it != ctx->graphs.end()) {
-      ge = &it->second;
-      slot_index = ge->slot;
-      s = &ctx->slots[slot_index];
-      st = harvest(ctx, *s, stream, true);
-      if (st == WF_ETIMEDOUT) ctx->sticky = WF_ETIMEDOUT;
-      else if (st != WF_OK) return st;
-    }
-  }
-  if (!s) {
-    st = acquire_slot(ctx, stream, &s, &slot_index);
-    if (st != WF_OK) return st;
-    // A slot that backs a cached graph is handed to this batch; drop that graph.
-    for (auto it = ctx->graphs.begin(); it != ctx->graphs.end();) {
-      if (it->second.slot == slot_index) {
-        hipGraphExecDestroy(it->second.exec);
-        hipGraphDestroy(it->second.graph);
-        it = ctx->graphs.erase(it);
-      } else {
-        ++it;
-      }
-    }
-  }
-  const uint32_t sent = sentinel_of(ps[0].dtype);
-  // Also on replay: a single-grid solve may have used this slot since, growing its
-  // handoff rows or arming them with another dtype's sentinel.
-  st = ensure_hand(*s, hand_total, sent, stream);
+  wf_status st = acquire_slot(ctx, &s);
   if (st != WF_OK) return st;
-  if (!ge) {
-    st = ensure_buf(&s->grids, &s->grids_cap, descs.size());
-    if (st != WF_OK) return st;
-    st = ensure_buf(&s->items, &s->items_cap, items.size());
-    if (st != WF_OK) return st;
-  }
-  for (size_t gi = 0; gi < descs.size(); ++gi) descs[gi].hand = s->hand + hand_off[gi];
-  // The tables are copied on the stream (pointers may differ between calls with the same
-  // shape); a replayed graph whose table is unchanged skips the copy.
-  const bool same_table = ge && ge->descs.size() == descs.size() &&
-                          std::memcmp(ge->descs.data(), descs.data(), descs.size() * sizeof(GridDesc)) == 0;
-  if (!same_table) {
-    WF_HIP(hipMemcpyAsync(s->grids, descs.data(), descs.size() * sizeof(GridDesc), hipMemcpyHostToDevice, stream));
-    if (!ge) WF_HIP(hipMemcpyAsync(s->items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, stream));
-    // The host arrays must outlive the asynchronous copies.
-    WF_HIP(hipStreamSynchronize(stream));
-  }
-
-  KArgs a;
-  std::memset(&a, 0, sizeof a);
+  st = ensure_hand(*s, hand_total, sentinel_of(ps[perm[0]].dtype), stream);
+  if (st == WF_OK) st = ensure_buf(&s->grids, &s->grids_cap, perm.size());
+  if (st == WF_OK) st = ensure_buf(&s->items, &s->items_cap, items.size());
+  if (st != WF_OK) return st;
+  std::vector<GridDesc> descs(perm.size());
+  for (size_t gi = 0; gi < perm.size(); ++gi) descs[gi] = make_desc(&ps[perm[gi]], W, s->hand + hand_off[gi]);
+  WF_HIP(hipMemcpyAsync(s->grids, descs.data(), descs.size() * sizeof(GridDesc), hipMemcpyHostToDevice, stream));
+  WF_HIP(hipMemcpyAsync(s->items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, stream));
+  WF_HIP(hipStreamSynchronize(stream));  // the host arrays must outlive the copies
+  KArgs a = base_args(ctx, s->ctl, (int64_t)items.size());
   a.grids = s->grids;
   a.items = s->items;
-  a.nitems = (int64_t)items.size();
-  a.ctl = s->ctl;
-  a.watchdog_ticks = ctx->watchdog_ticks;
-
-  if (use_graph) {
-    if (!ge) {
-      hipStream_t cap = nullptr;
-      WF_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-      GraphEntry e;
-      e.slot = slot_index;
-      hipError_t err = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-      if (err == hipSuccess) {
-        launch_fill_u32(s->ctl, 0u, CTL_WORDS, cap);
-        launch_sweep(ps[0].dtype, ps[0].rule, W, nwg, a, cap);
-        err = hipStreamEndCapture(cap, &e.graph);
-      }
-      if (err == hipSuccess) err = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0);
-      hipStreamDestroy(cap);
-      if (err != hipSuccess) return fail(WF_EHIP, std::string("graph capture: ") + hipGetErrorString(err));
-      ge = &(ctx->graphs[key] = e);
-    }
-    if (!same_table) ge->descs = descs;
-    WF_HIP(hipGraphLaunch(ge->exec, stream));
-  } else {
-    WF_HIP(launch_fill_u32(s->ctl, 0u, CTL_WORDS, stream));
-    WF_HIP(launch_sweep(ps[0].dtype, ps[0].rule, W, nwg, a, stream));
-  }
+  WF_HIP(launch_fill_u32(s->ctl, 0u, CTL_WORDS, stream));
+  WF_HIP(launch_sweep(ps[perm[0]].dtype, ps[perm[0]].rule, W, batch_wgs(ctx, W, a.nitems, max_wgs), a, stream));
   return finish_launch(*s, stream);
 }
 
-// Autotuning: the first batch of a given shape signature (and no explicit
-// waves_per_wg / order) is run twice at every candidate configuration, the
-// second run timed with events on the caller's stream, and the fastest is kept
-// for that signature.  Every trial computes the full, correct result.
-static std::string shape_signature(const wf_problem* ps, int64_t count) {
-  return batch_key(ps, count, 0, 0, 0);
+static std::vector<int64_t> shape_of(const wf_problem* ps, int64_t count) {
+  std::vector<int64_t> v((size_t)count * 3);
+  for (int64_t i = 0; i < count; ++i) {
+    v[3 * i] = ps[i].m;
+    v[3 * i + 1] = ps[i].n;
+    v[3 * i + 2] = ps[i].mode;
+  }
+  return v;
 }
 
+// A cached batch plan: found by the batch's shapes and configuration, replayed with
+// two lanes in turn.  Its tables are rebuilt only when the problem array changes.
+static wf_status batched_plan(wf_ctx* ctx, const wf_problem* ps, int64_t count, int W, int order, int max_wgs,
+                              bool use_graph, hipStream_t stream) {
+  const uint64_t cfg[5] = {(uint64_t)count, (uint64_t)W, (uint64_t)order, (uint64_t)max_wgs, (uint64_t)use_graph};
+  uint64_t h = fnv1a(1469598103934665603ull, cfg, sizeof cfg);
+  const int dtype = ps[0].dtype, rule = ps[0].rule;
+  const uint64_t dr[2] = {(uint64_t)dtype, (uint64_t)rule};
+  h = fnv1a(h, dr, sizeof dr);
+  BatchPlanEntry* e = nullptr;
+  // Fast path: the very problem array of the plan's last launch.
+  for (auto& p : ctx->plans)
+    if (p->probs.size() == (size_t)count && p->W == W && p->order == order && p->use_graph == use_graph &&
+        p->dtype == dtype && p->rule == rule &&
+        std::memcmp(p->probs.data(), ps, (size_t)count * sizeof(wf_problem)) == 0) {
+      e = p.get();
+      break;
+    }
+  if (!e) {
+    std::vector<int64_t> shape = shape_of(ps, count);
+    h = fnv1a(h, shape.data(), shape.size() * sizeof(int64_t));
+    for (auto& p : ctx->plans)
+      if (p->hash == h && p->shape == shape && p->W == W && p->order == order && p->use_graph == use_graph &&
+          p->dtype == dtype && p->rule == rule && p->probs.size() == (size_t)count) {
+        e = p.get();
+        break;
+      }
+    if (!e) {
+      // New plan; evict the least recently used one beyond MAX_PLANS.
+      if ((int)ctx->plans.size() >= wf_ctx::MAX_PLANS) {
+        size_t lru = 0;
+        for (size_t i = 1; i < ctx->plans.size(); ++i)
+          if (ctx->plans[i]->last_use < ctx->plans[lru]->last_use) lru = i;
+        drop_plan(*ctx->plans[lru], ctx);
+        ctx->plans.erase(ctx->plans.begin() + (long)lru);
+      }
+      std::unique_ptr<BatchPlanEntry> n(new BatchPlanEntry);
+      n->hash = h;
+      n->shape = std::move(shape);
+      n->W = W;
+      n->order = order;
+      n->dtype = dtype;
+      n->rule = rule;
+      n->use_graph = use_graph;
+      build_work(ps, count, W, order, n->perm, n->items, n->hand_off, n->hand_total);
+      n->nwg = batch_wgs(ctx, W, (int64_t)n->items.size(), max_wgs);
+      ctx->plans.push_back(std::move(n));
+      e = ctx->plans.back().get();
+    }
+    e->probs.assign(ps, ps + count);
+  }
+  e->last_use = ++ctx->use_clock;
+  if (e->items.empty()) return WF_OK;
+  BatchPlanEntry::Lane& L = e->lanes[e->replays % 2];
+  ++e->replays;
+  if (L.slot < 0) {
+    Slot* s = nullptr;
+    wf_status st = acquire_slot(ctx, &s);
+    if (st != WF_OK) return st;
+    s->reserved = true;
+    for (size_t i = 0; i < ctx->slots.size(); ++i)
+      if (ctx->slots[i].get() == s) L.slot = (int)i;
+  }
+  Slot& s = *ctx->slots[(size_t)L.slot];
+  // The lane's previous replay must have finished before its tables or error word are reused.
+  wf_status st = note(ctx, harvest(s, true));
+  if (st != WF_OK) return st;
+  st = ensure_hand(s, e->hand_total, sentinel_of(dtype), stream);
+  if (st == WF_OK) st = ensure_buf(&s.grids, &s.grids_cap, e->perm.size());
+  if (st == WF_OK) st = ensure_buf(&s.items, &s.items_cap, e->items.size());
+  if (st != WF_OK) return st;
+  if (!L.items_loaded) {
+    // Synchronous: the plan's work list never changes, so this happens once per lane.
+    WF_HIP(hipMemcpy(s.items, e->items.data(), e->items.size() * sizeof(Item), hipMemcpyHostToDevice));
+    L.items_loaded = true;
+  }
+  std::vector<GridDesc> descs(e->perm.size());
+  for (size_t gi = 0; gi < e->perm.size(); ++gi) descs[gi] = make_desc(&ps[e->perm[gi]], W, s.hand + e->hand_off[gi]);
+  if (L.descs.size() != descs.size() ||
+      std::memcmp(L.descs.data(), descs.data(), descs.size() * sizeof(GridDesc)) != 0) {
+    if (!L.staging) WF_HIP(hipHostMalloc((void**)&L.staging, descs.size() * sizeof(GridDesc), hipHostMallocDefault));
+    std::memcpy(L.staging, descs.data(), descs.size() * sizeof(GridDesc));
+    WF_HIP(hipMemcpyAsync(s.grids, L.staging, descs.size() * sizeof(GridDesc), hipMemcpyHostToDevice, stream));
+    L.descs = std::move(descs);
+  }
+  KArgs a = base_args(ctx, s.ctl, (int64_t)e->items.size());
+  a.grids = s.grids;
+  a.items = s.items;
+  if (use_graph) {
+    if (!L.exec) {
+      hipStream_t cap = nullptr;
+      WF_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      hipError_t err = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      if (err == hipSuccess) {
+        launch_fill_u32(s.ctl, 0u, CTL_WORDS, cap);
+        launch_sweep(dtype, rule, W, e->nwg, a, cap);
+        err = hipStreamEndCapture(cap, &L.graph);
+      }
+      if (err == hipSuccess) err = hipGraphInstantiate(&L.exec, L.graph, nullptr, nullptr, 0);
+      hipStreamDestroy(cap);
+      if (err != hipSuccess) return fail(WF_EHIP, std::string("graph capture: ") + hipGetErrorString(err));
+    }
+    WF_HIP(hipGraphLaunch(L.exec, stream));
+  } else {
+    WF_HIP(launch_fill_u32(s.ctl, 0u, CTL_WORDS, stream));
+    WF_HIP(launch_sweep(dtype, rule, W, e->nwg, a, stream));
+  }
+  return finish_launch(s, stream);
+}
+
+// ------------------------------------------------------------- autotuning
+// Shape class of a batch: dtype, rule, modes, and the binary magnitudes of the grid
+// count, the total cells, the tallest and the widest grid.  Batches of one class
+// share a tuned configuration.
+static std::string shape_class(const wf_problem* ps, int64_t count) {
+  int64_t cells = 0, mm = 0, mn = 0, full = 0, edges = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    cells += ps[i].m * ps[i].n;
+    mm = std::max(mm, ps[i].m);
+    mn = std::max(mn, ps[i].n);
+    (ps[i].mode == WF_MODE_FULL ? full : edges)++;
+  }
+  auto lg = [](int64_t v) { return v > 0 ? (int)std::floor(std::log2((double)v)) : -1; };
+  char buf[128];
+  snprintf(buf, sizeof buf, "d%d.r%d.%s.g%d.c%d.m%d.n%d", ps[0].dtype, ps[0].rule,
+           edges == 0 ? "full" : (full == 0 ? "edges" : "mixed"), lg(count), lg(cells), lg(mm), lg(mn));
+  return buf;
+}
+
+// Candidates: waves per workgroup x work order x workgroup count (every resident
+// workgroup, or half of them).  Each runs twice back to back on `stream`, the second
+// run timed with events (its host set-up overlaps the first run on the device).
 static wf_status autotune(wf_ctx* ctx, const wf_problem* ps, int64_t count, int max_wgs, hipStream_t stream,
-                          int* W_out, int* order_out) {
-  const std::string sig = shape_signature(ps, count);
-  auto it = ctx->tuned.find(sig);
+                          TuneEntry* out) {
+  const std::string cls = shape_class(ps, count);
+  auto it = ctx->tuned.find(cls);
   if (it != ctx->tuned.end()) {
-    *W_out = it->second.first;
-    *order_out = it->second.second;
+    *out = it->second;
     return WF_OK;
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   WF_HIP(hipEventCreate(&e0));
   WF_HIP(hipEventCreate(&e1));
-  float best = -1.f;
-  int bw = 1, bo = 1;
-  static const int Ws[] = {1, 2};
+  TuneEntry best;
+  best.ms = -1;
   wf_status st = WF_OK;
-  for (int W : Ws) {
+  for (int W = 1; W <= 2 && st == WF_OK; ++W) {
+    const int resident = ctx->num_cus * wgs_per_cu(W);
+    const int wg_opts[2] = {max_wgs > 0 ? std::min(max_wgs, resident) : resident,
+                            std::max(1, (max_wgs > 0 ? std::min(max_wgs, resident) : resident) / 2)};
     for (int order = 1; order <= 2 && st == WF_OK; ++order) {
-      // Two runs back to back, timing the second: its host-side set-up overlaps the
-      // first run on the device, so the events bracket device time only.
-      st = batched_run(ctx, ps, count, W, order, max_wgs, false, stream);
-      if (st != WF_OK) break;
-      hipError_t e = hipEventRecord(e0, stream);
-      if (e == hipSuccess) st = batched_run(ctx, ps, count, W, order, max_wgs, false, stream);
-      if (st == WF_OK && e == hipSuccess) e = hipEventRecord(e1, stream);
-      if (st == WF_OK && e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (st == WF_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (st == WF_OK && e != hipSuccess) st = fail(WF_EHIP, std::string("autotune: ") + hipGetErrorString(e));
-      if (st != WF_OK) break;
-      st = report_sticky(ctx);
-      if (st != WF_OK) break;
-      if (best < 0.f || ms < best) {
-        best = ms;
-        bw = W;
-        bo = order;
+      for (int wi = 0; wi < 2 && st == WF_OK; ++wi) {
+        const int wgs = wg_opts[wi];
+        st = batched_once(ctx, ps, count, W, order, wgs, stream);
+        if (st != WF_OK) break;
+        hipError_t e = hipEventRecord(e0, stream);
+        if (e == hipSuccess) st = batched_once(ctx, ps, count, W, order, wgs, stream);
+        if (st == WF_OK && e == hipSuccess) e = hipEventRecord(e1, stream);
+        if (st == WF_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (st == WF_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (st == WF_OK && e != hipSuccess) st = fail(WF_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+        if (st != WF_OK) break;
+        st = report_sticky(ctx);
+        if (st != WF_OK) break;
+        if (best.ms < 0 || ms < best.ms) {
+          best.ms = ms;
+          best.W = W;
+          best.order = order;
+          best.wgs = wgs;
+        }
       }
     }
-    if (st != WF_OK) break;
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (st != WF_OK) return st;
-  ctx->tuned[sig] = std::make_pair(bw, bo);
-  *W_out = bw;
-  *order_out = bo;
+  ctx->tuned[cls] = best;
+  save_tune_cache(ctx);
+  *out = best;
   return WF_OK;
 }
 
@@ -556,12 +820,9 @@ extern "C" wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t
   wf_tuning tun;
   std::memset(&tun, 0, sizeof tun);
   if (t) tun = *t;
-  for (int i = 0; i < 4; ++i)
-    if (tun.reserved[i] != 0) return fail(WF_EINVAL, "wf_tuning.reserved must be 0");
-  if (tun.waves_per_wg < 0 || tun.waves_per_wg > 2) return fail(WF_EINVAL, "waves_per_wg must be 0, 1 or 2");
-  if (tun.max_wgs < 0 || tun.order < 0 || tun.order > 2 || tun.use_graph < -1 || tun.use_graph > 1)
-    return fail(WF_EINVAL, "bad tuning value");
-  wf_status st = set_device(ctx);
+  wf_status st = check_tuning(tun);
+  if (st != WF_OK) return st;
+  st = set_device(ctx);
   if (st != WF_OK) return st;
   st = report_sticky(ctx);
   if (st != WF_OK) return st;
@@ -569,16 +830,41 @@ extern "C" wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t
   bool any = false;
   for (int64_t i = 0; i < count && !any; ++i) any = ps[i].m > 0 && ps[i].n > 0;
   if (!any) return WF_OK;
-  int W = tun.waves_per_wg, order = tun.order;
+  int W = tun.waves_per_wg, order = tun.order, wgs = tun.max_wgs;
   if (W == 0 && order == 0 && tun.use_graph != -1) {
-    st = autotune(ctx, ps, count, tun.max_wgs, stream, &W, &order);
+    TuneEntry te;
+    st = autotune(ctx, ps, count, tun.max_wgs, stream, &te);
     if (st != WF_OK) return st;
+    W = te.W;
+    order = te.order;
+    wgs = te.wgs;
   }
-  if (W == 0) {
-    int64_t max_m = 0;
-    for (int64_t i = 0; i < count; ++i) max_m = std::max(max_m, ps[i].m);
-    W = choose_waves(max_m / 2 > 0 ? max_m / 2 : 1);
-  }
+  if (W == 0) W = 1;
   if (order == 0) order = 1;
-  return batched_run(ctx, ps, count, W, order, tun.max_wgs, tun.use_graph == 1, stream);
+  if (tun.use_graph == 1) return batched_plan(ctx, ps, count, W, order, wgs, true, stream);
+  return batched_once(ctx, ps, count, W, order, wgs, stream);
+}
+
+// ------------------------------------------------------------- measurement
+namespace wfk {
+hipError_t launch_chain_probe(float* out, uint64_t* ticks, int steps, hipStream_t stream);
+}
+
+extern "C" wf_status wf_measure_step_ns(wf_ctx* ctx, int64_t steps, double* ns_per_step) {
+  if (!ctx || !ns_per_step) return fail(WF_EINVAL, "ctx and ns_per_step must not be NULL");
+  if (steps < 16 || steps > ((int64_t)1 << 30)) return fail(WF_EINVAL, "steps must be 16 .. 2^30");
+  wf_status st = set_device(ctx);
+  if (st != WF_OK) return st;
+  float* out = nullptr;
+  uint64_t* ticks = nullptr;
+  WF_HIP(hipMalloc(&out, 64 * sizeof(float)));
+  WF_HIP(hipMalloc(&ticks, sizeof(uint64_t)));
+  uint64_t h = 0;
+  hipError_t e = launch_chain_probe(out, ticks, (int)(steps / 16 * 16), nullptr);
+  if (e == hipSuccess) e = hipMemcpy(&h, ticks, sizeof h, hipMemcpyDeviceToHost);
+  hipFree(out);
+  hipFree(ticks);
+  if (e != hipSuccess) return fail(WF_EHIP, std::string("step probe: ") + hipGetErrorString(e));
+  *ns_per_step = (double)h * 10.0 / (double)(steps / 16 * 16);  // the wall clock runs at 100 MHz
+  return WF_OK;
 }

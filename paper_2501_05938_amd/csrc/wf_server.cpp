@@ -5,18 +5,29 @@
 //
 // One server thread owns every HIP call of the server.  Per pass it
 //   1. retires launches whose completion event has fired (results stay in
-//      server memory until wf_release),
-//   2. admits queued requests in arrival order while their memory fits the
-//      budget (a first-fit arena carved from one device allocation),
-//   3. packs the admitted requests that share dtype and rule into one launch
-//      on a free stream: host inputs are copied in, handoff rows are armed,
-//      the descriptor table and work list are uploaded from pinned staging,
-//      and the persistent kernel runs their bands in ticket order.
+//      server memory until wf_release) and frees the staging of host copies
+//      that have landed,
+//   2. admits queued requests while their memory fits the budget: in arrival
+//      order, but a request that does not fit yet lets smaller ones behind it
+//      in until it has waited `max_wait_skip_us` (then admission waits for it);
+//      a host input is copied to the device on a copy stream at admission,
+//   3. packs admitted requests that share dtype and rule into one launch on a
+//      free stream: the launch stream waits for its requests' copies (or for
+//      the caller's ready events of device inputs), seeded inputs are
+//      generated on the device, handoff rows are armed, the descriptor table
+//      and work list are uploaded from pinned staging, and the persistent
+//      kernel runs their bands in ticket order.
 // Launches on different streams overlap on the device: a launch's workgroups
 // retire as its ticket list runs out, and the next launch's workgroups take
 // their place.  Each launch has its own ticket counter, and a band only waits
 // on a band of the same launch with a smaller ticket, so concurrent launches
 // cannot deadlock one another.
+//
+// Copies of host inputs on their own streams overlap the sweeps of earlier
+// launches: the copy/compute overlap that arXiv 2501.05938 builds its streamed
+// time model on (Section 1; Section 2.2, Eq. 2).  Requests are then a two-stage
+// flow shop (copy, then sweep), whose makespan is the max-plus recurrence of the
+// sweep's max rule over a (requests x 2 stages) grid.
 #include "../../include/wf.h"
 #include "wf_host.h"
 #include "wf_internal.h"
@@ -46,21 +57,15 @@ double now_s() {
 constexpr size_t ALIGN = 256;
 size_t round_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
-// First-fit allocator over one device allocation, with coalescing on release.
+// First-fit allocator over one block of memory, with coalescing on release.
 class Arena {
  public:
-  wf_status init(size_t bytes) {
-    size_ = round_up(bytes);
-    if (hipMalloc(&base_, size_) != hipSuccess) {
-      base_ = nullptr;
-      return fail(WF_ENOMEM, "cannot allocate the server's device memory budget");
-    }
-    free_[0] = size_;
-    return WF_OK;
-  }
-  void destroy() {
-    if (base_) hipFree(base_);
-    base_ = nullptr;
+  void reset(char* base, size_t bytes) {
+    base_ = base;
+    size_ = bytes / ALIGN * ALIGN;
+    free_.clear();
+    if (size_) free_[0] = size_;
+    in_use_ = peak_ = 0;
   }
   bool alloc(size_t bytes, size_t* off) {
     bytes = round_up(bytes);
@@ -94,13 +99,13 @@ class Arena {
       }
     }
   }
-  char* base() const { return (char*)base_; }
+  char* base() const { return base_; }
   size_t size() const { return size_; }
   size_t in_use() const { return in_use_; }
   size_t peak() const { return peak_; }
 
  private:
-  void* base_ = nullptr;
+  char* base_ = nullptr;
   size_t size_ = 0, in_use_ = 0, peak_ = 0;
   std::map<size_t, size_t> free_;  // offset -> length
 };
@@ -113,8 +118,8 @@ struct Req {
   wf_status err = WF_OK;
   std::string msg;
   double t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
-  // Server memory: one arena block holding, in order, the input copy (host
-  // inputs only), the full output (FULL mode), last row, last column, final
+  // Server memory: one arena block holding, in order, the input copy (host and
+  // seeded inputs), the full output (FULL mode), last row, last column, final
   // cell and the handoff rows.
   size_t off = 0, bytes = 0;
   bool has_block = false;
@@ -126,7 +131,11 @@ struct Req {
   void* final_cell = nullptr;
   uint32_t* hand = nullptr;
   size_t hand_n = 0;
+  hipEvent_t copied = nullptr;  // recorded on a copy stream after the input landed (host inputs)
 };
+
+bool host_input(const wf_request& r) { return r.input_kind == WF_INPUT_HOST || r.input_kind == WF_INPUT_HOST_PINNED; }
+bool owns_input(const wf_request& r) { return host_input(r) || r.input_kind == WF_INPUT_SEED; }
 
 // Byte layout of a request's block.
 struct Layout {
@@ -138,7 +147,7 @@ Layout layout_of(const wf_request& r) {
   Layout L;
   size_t at = 0;
   const size_t m = (size_t)r.m, n = (size_t)r.n;
-  if (r.input_kind == WF_INPUT_HOST) {
+  if (owns_input(r)) {
     L.in = at;
     at += round_up(m * n * 4);
   }
@@ -171,12 +180,20 @@ struct LaunchSlot {
   GridDesc* h_grids = nullptr;  // pinned staging, valid until `done` fires
   Item* h_items = nullptr;
   size_t h_grids_cap = 0, h_items_cap = 0;
-  unsigned char* h_stage = nullptr;  // pinned staging of host inputs, valid until `done` fires
+  unsigned char* h_stage = nullptr;  // pinned staging of host inputs without copy streams
   size_t h_stage_cap = 0;
   uint32_t* host_err = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
   std::vector<uint64_t> tickets;
+};
+
+// A host input in flight on a copy stream: its staging is freed once `ev` has fired.
+struct Copy {
+  hipEvent_t ev;
+  size_t stage_off, stage_bytes;
+  bool staged;
+  uint64_t ticket;
 };
 
 template <class T>
@@ -206,11 +223,23 @@ wf_status grow_host(T** p, size_t* cap, size_t need) {
 
 }  // namespace
 
+// Seeded input generation for WF_INPUT_SEED requests (wf_seed.hip).
+namespace wfk {
+hipError_t launch_seed_fill(void* dst, int dtype, int64_t m, int64_t n, uint64_t seed, hipStream_t stream);
+}
+
 struct wf_server {
   wf_ctx* ctx = nullptr;
   wf_server_opts opts{};
-  Arena arena;
+  void* dev_base = nullptr;
+  Arena arena;                    // device budget
+  void* pin_base = nullptr;
+  Arena staging;                  // pinned staging of pageable host inputs (copy streams only)
   std::vector<LaunchSlot> slots;
+  std::vector<hipStream_t> copy_streams;
+  size_t next_copy = 0;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<Copy> copying;
   std::mutex mu;
   std::condition_variable cv;
   std::thread thread;
@@ -224,26 +253,33 @@ struct wf_server {
   std::string thread_error;       // a HIP failure inside the server thread
 
   void run();
-  void retire(LaunchSlot& L, double t);
+  void retire(LaunchSlot& L, double t, hipError_t q);
+  void reap_copies();
   void admit(double t);
+  bool try_admit(Req& q, uint64_t ticket, double t);
   bool launch_one(std::unique_lock<std::mutex>& lk);
   wf_status enqueue(LaunchSlot& L, std::vector<Req*>& batch, int W, int dtype, int rule);
+  wf_status start_copy(Req& q, Copy* c);
 };
 
-void wf_server::retire(LaunchSlot& L, double t) {
-  const bool timed_out = *L.host_err != DEV_OK;
+void wf_server::retire(LaunchSlot& L, double t, hipError_t q) {
+  const bool timed_out = q == hipSuccess && *L.host_err != DEV_OK;
   *L.host_err = DEV_OK;
   for (uint64_t tk : L.tickets) {
     auto it = reqs.find(tk);
     if (it == reqs.end()) continue;
-    Req& q = it->second;
-    q.t_done = t;
-    if (timed_out) {
-      q.state = FAILED;
-      q.err = WF_ETIMEDOUT;
-      q.msg = "device watchdog fired in the request's launch";
+    Req& r = it->second;
+    r.t_done = t;
+    if (q != hipSuccess) {
+      r.state = FAILED;
+      r.err = WF_EHIP;
+      r.msg = std::string("the request's launch failed: ") + hipGetErrorString(q);
+    } else if (timed_out) {
+      r.state = FAILED;
+      r.err = WF_ETIMEDOUT;
+      r.msg = "device watchdog fired in the request's launch";
     } else {
-      q.state = DONE;
+      r.state = DONE;
     }
   }
   L.tickets.clear();
@@ -251,43 +287,128 @@ void wf_server::retire(LaunchSlot& L, double t) {
   --inflight;
 }
 
-void wf_server::admit(double t) {
-  while (!queue.empty()) {
-    Req& q = reqs[queue.front()];
-    size_t off = 0;
-    if (!arena.alloc(q.bytes, &off)) break;  // wait for memory: admission stays in arrival order
-    const Layout Lo = layout_of(q.r);
-    char* b = arena.base() + off;
-    q.off = off;
-    q.has_block = true;
-    if (q.r.input_kind == WF_INPUT_HOST) {
-      q.in = b + Lo.in;
-      q.ld_in = q.r.n;
-    } else {
-      q.in = q.r.input;
-      q.ld_in = q.r.ld_input;
+void wf_server::reap_copies() {
+  for (size_t i = 0; i < copying.size();) {
+    if (hipEventQuery(copying[i].ev) == hipErrorNotReady) {
+      ++i;
+      continue;
     }
-    q.out = q.r.mode == WF_MODE_FULL ? (void*)(b + Lo.out) : nullptr;
-    q.last_row = b + Lo.last_row;
-    q.last_col = b + Lo.last_col;
-    q.final_cell = b + Lo.final_cell;
-    q.hand = (uint32_t*)(b + Lo.hand);
-    q.hand_n = Lo.hand_n;
-    q.state = ADMITTED;
-    q.t_admit = t;
-    admitted.push_back(queue.front());
-    queue.pop_front();
+    if (copying[i].staged) staging.release(copying[i].stage_off, copying[i].stage_bytes);
+    // The copy has landed: a launch not enqueued yet need not wait for it (the event
+    // goes back to the pool and may be recorded again for another copy).
+    auto it = reqs.find(copying[i].ticket);
+    if (it != reqs.end() && it->second.copied == copying[i].ev) it->second.copied = nullptr;
+    event_pool.push_back(copying[i].ev);
+    copying[i] = copying.back();
+    copying.pop_back();
+  }
+}
+
+// Copy a host input to its device block on the next copy stream (pageable inputs go
+// through pinned staging first; pinned ones are copied directly).
+wf_status wf_server::start_copy(Req& q, Copy* c) {
+  const size_t row = (size_t)q.r.n * 4, bytes = row * (size_t)q.r.m;
+  hipStream_t cs = copy_streams[next_copy++ % copy_streams.size()];
+  c->staged = false;
+  const char* src = (const char*)q.r.input;
+  const bool dense = q.r.ld_input == q.r.n;
+  if (q.r.input_kind == WF_INPUT_HOST_PINNED) {
+    if (dense) {
+      WF_HIP(hipMemcpyAsync((void*)q.in, src, bytes, hipMemcpyHostToDevice, cs));
+    } else {
+      WF_HIP(hipMemcpy2DAsync((void*)q.in, row, src, (size_t)q.r.ld_input * 4, row, (size_t)q.r.m,
+                              hipMemcpyHostToDevice, cs));
+    }
+  } else {
+    char* st = staging.base() + c->stage_off;
+    for (int64_t i = 0; i < q.r.m; ++i) std::memcpy(st + (size_t)i * row, src + (size_t)i * (size_t)q.r.ld_input * 4, row);
+    WF_HIP(hipMemcpyAsync((void*)q.in, st, bytes, hipMemcpyHostToDevice, cs));
+    c->staged = true;
+  }
+  WF_HIP(hipEventRecord(c->ev, cs));
+  q.copied = c->ev;
+  return WF_OK;
+}
+
+bool wf_server::try_admit(Req& q, uint64_t ticket, double t) {
+  const bool copy_now = host_input(q.r) && !copy_streams.empty();
+  const size_t stage_bytes = (size_t)q.r.m * (size_t)q.r.n * 4;
+  Copy c{nullptr, 0, 0, false, ticket};
+  if (copy_now && q.r.input_kind == WF_INPUT_HOST && !staging.alloc(stage_bytes, &c.stage_off)) return false;
+  size_t off = 0;
+  if (!arena.alloc(q.bytes, &off)) {
+    if (copy_now && q.r.input_kind == WF_INPUT_HOST) staging.release(c.stage_off, stage_bytes);
+    return false;
+  }
+  const Layout Lo = layout_of(q.r);
+  char* b = arena.base() + off;
+  q.off = off;
+  q.has_block = true;
+  if (owns_input(q.r)) {
+    q.in = b + Lo.in;
+    q.ld_in = q.r.n;
+  } else {
+    q.in = q.r.input;
+    q.ld_in = q.r.ld_input;
+  }
+  q.out = q.r.mode == WF_MODE_FULL ? (void*)(b + Lo.out) : nullptr;
+  q.last_row = b + Lo.last_row;
+  q.last_col = b + Lo.last_col;
+  q.final_cell = b + Lo.final_cell;
+  q.hand = (uint32_t*)(b + Lo.hand);
+  q.hand_n = Lo.hand_n;
+  q.state = ADMITTED;
+  q.t_admit = t;
+  if (copy_now) {
+    c.stage_bytes = stage_bytes;
+    if (event_pool.empty()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) event_pool.push_back(e);
+    }
+    wf_status st = WF_EHIP;
+    if (!event_pool.empty()) {
+      c.ev = event_pool.back();
+      event_pool.pop_back();
+      st = start_copy(q, &c);
+    }
+    if (st != WF_OK) {
+      q.state = FAILED;
+      q.err = st == WF_EHIP && event_pool.empty() && !c.ev ? WF_ENOMEM : st;
+      q.msg = wf_last_error();
+      q.t_done = t;
+      if (c.ev) event_pool.push_back(c.ev);
+      if (q.r.input_kind == WF_INPUT_HOST) staging.release(c.stage_off, stage_bytes);
+      return true;
+    }
+    copying.push_back(c);
+  }
+  admitted.push_back(ticket);
+  return true;
+}
+
+void wf_server::admit(double t) {
+  // Arrival order; a request that does not fit yet lets requests behind it in until it
+  // has waited max_wait_skip_us, after which nothing overtakes it.
+  int skipped = 0;
+  for (auto it = queue.begin(); it != queue.end();) {
+    Req& q = reqs[*it];
+    if (try_admit(q, *it, t)) {
+      it = queue.erase(it);
+      continue;
+    }
+    if (t - q.t_submit > opts.max_wait_skip_us * 1e-6 || ++skipped > 64) break;
+    ++it;
   }
 }
 
 wf_status wf_server::enqueue(LaunchSlot& L, std::vector<Req*>& batch, int W, int dtype, int rule) {
   hipStream_t s = L.stream;
-  // Host inputs go through the slot's pinned staging buffer: a copy from pageable memory
-  // is staged synchronously by the runtime in the calling thread, which would make the
-  // server thread block on the device (and on other threads' device-wide waits).
+  // Host inputs without copy streams go through the slot's pinned staging buffer on the
+  // launch stream: a copy from pageable memory is staged synchronously by the runtime in
+  // the calling thread, which would make the server thread block on the device.
   size_t stage = 0;
   for (Req* q : batch)
-    if (q->r.input_kind == WF_INPUT_HOST) stage += (size_t)q->r.m * (size_t)q->r.n * 4;
+    if (host_input(q->r) && !q->copied) stage += (size_t)q->r.m * (size_t)q->r.n * 4;
   if (stage) {
     wf_status st = grow_host(&L.h_stage, &L.h_stage_cap, stage);
     if (st != WF_OK) return st;
@@ -295,12 +416,18 @@ wf_status wf_server::enqueue(LaunchSlot& L, std::vector<Req*>& batch, int W, int
   const uint32_t sent = sentinel_of(dtype);
   size_t at = 0;
   for (Req* q : batch) {
-    if (q->r.input_kind == WF_INPUT_HOST) {
+    if (q->copied) {
+      WF_HIP(hipStreamWaitEvent(s, q->copied, 0));
+    } else if (host_input(q->r)) {
       const size_t row = (size_t)q->r.n * 4, bytes = row * (size_t)q->r.m;
       for (int64_t i = 0; i < q->r.m; ++i)
         std::memcpy(L.h_stage + at + (size_t)i * row, (const char*)q->r.input + (size_t)i * (size_t)q->r.ld_input * 4, row);
       WF_HIP(hipMemcpyAsync((void*)q->in, L.h_stage + at, bytes, hipMemcpyHostToDevice, s));
       at += bytes;
+    } else if (q->r.input_kind == WF_INPUT_SEED) {
+      WF_HIP(launch_seed_fill((void*)q->in, q->r.dtype, q->r.m, q->r.n, q->r.seed, s));
+    } else if (q->r.ready_event) {
+      WF_HIP(hipStreamWaitEvent(s, (hipEvent_t)q->r.ready_event, 0));
     }
     if (q->hand_n) WF_HIP(launch_fill_u32(q->hand, sent, (int64_t)q->hand_n, s));
   }
@@ -336,13 +463,9 @@ wf_status wf_server::enqueue(LaunchSlot& L, std::vector<Req*>& batch, int W, int
   }
   WF_HIP(hipMemcpyAsync(L.d_grids, L.h_grids, batch.size() * sizeof(GridDesc), hipMemcpyHostToDevice, s));
   WF_HIP(hipMemcpyAsync(L.d_items, L.h_items, nitems * sizeof(Item), hipMemcpyHostToDevice, s));
-  KArgs a;
-  std::memset(&a, 0, sizeof a);
+  KArgs a = base_args(ctx, L.ctl, (int64_t)nitems);
   a.grids = L.d_grids;
   a.items = L.d_items;
-  a.nitems = (int64_t)nitems;
-  a.ctl = L.ctl;
-  a.watchdog_ticks = ctx->watchdog_ticks;
   const int nwg = (int)std::min<int64_t>((int64_t)nitems, (int64_t)ctx->num_cus * wgs_per_cu(W));
   WF_HIP(launch_fill_u32(L.ctl, 0u, CTL_WORDS, s));
   WF_HIP(launch_sweep(dtype, rule, W, nwg, a, s));
@@ -382,7 +505,7 @@ bool wf_server::launch_one(std::unique_lock<std::mutex>& lk) {
   L->busy = true;
   L->tickets = tickets;
   ++inflight;
-  const int W = choose_waves(max_m / 2 > 0 ? max_m / 2 : 1);
+  const int W = choose_waves(max_m);
   const double t = now_s();
   for (Req* q : batch) q->t_launch = t;
   // Requests in `batch` are LAUNCHED: wf_release refuses them, so the pointers stay valid.
@@ -413,16 +536,22 @@ void wf_server::run() {
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     const double t = now_s();
-    for (auto& L : slots)
-      if (L.busy && hipEventQuery(L.done) == hipSuccess) retire(L, t);
+    for (auto& L : slots) {
+      if (!L.busy) continue;
+      // Any result but "not ready" ends the launch: success, or a failed launch whose
+      // requests are then reported as failed.
+      const hipError_t q = hipEventQuery(L.done);
+      if (q != hipErrorNotReady) retire(L, t, q);
+    }
+    reap_copies();
     if (!stop) admit(t);
     bool launched = false;
     while (!stop && launch_one(lk)) launched = true;
     if (stop && inflight == 0) break;
     if (launched) continue;
     const uint64_t seen = epoch;
-    if (inflight > 0) {
-      // Launches in flight: look at their events again shortly, or at once on a submit.
+    if (inflight > 0 || !copying.empty()) {
+      // Work in flight: look at its events again shortly, or at once on a submit.
       cv.wait_for(lk, std::chrono::microseconds(20), [&] { return stop || epoch != seen; });
     } else {
       // Idle (or waiting for memory held by finished requests): sleep until something changes.
@@ -438,27 +567,64 @@ extern "C" wf_status wf_server_create(wf_ctx* ctx, const wf_server_opts* opts, w
   wf_server_opts o;
   std::memset(&o, 0, sizeof o);
   if (opts) o = *opts;
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
     if (o.reserved[i] != 0) return fail(WF_EINVAL, "wf_server_opts.reserved must be 0");
-  if (o.hbm_budget_bytes < 0 || o.max_inflight < 0 || o.max_batch < 0) return fail(WF_EINVAL, "negative option");
+  if (o.hbm_budget_bytes < 0 || o.max_inflight < 0 || o.max_batch < 0 || o.copy_streams < 0 ||
+      o.staging_bytes < 0 || o.max_wait_skip_us < 0)
+    return fail(WF_EINVAL, "negative option");
   if (o.hbm_budget_bytes == 0) o.hbm_budget_bytes = (int64_t)64 << 30;
   if (o.max_inflight == 0) o.max_inflight = 4;
   if (o.max_batch == 0) o.max_batch = 256;
-  if (o.max_inflight > 32) return fail(WF_EINVAL, "max_inflight above 32");
+  if (o.staging_bytes == 0) o.staging_bytes = (int64_t)256 << 20;
+  if (o.max_wait_skip_us == 0) o.max_wait_skip_us = 20000;
+  if (o.max_inflight > 32 || o.copy_streams > 8) return fail(WF_EINVAL, "max_inflight above 32 or copy_streams above 8");
   wf_status st = set_device(ctx);
   if (st != WF_OK) return st;
   std::unique_ptr<wf_server> s(new wf_server);
   s->ctx = ctx;
   s->opts = o;
-  st = s->arena.init((size_t)o.hbm_budget_bytes);
-  if (st != WF_OK) return st;
+  if (hipMalloc(&s->dev_base, (size_t)o.hbm_budget_bytes) != hipSuccess) {
+    s->dev_base = nullptr;
+    return fail(WF_ENOMEM, "cannot allocate the server's device memory budget");
+  }
+  s->arena.reset((char*)s->dev_base, (size_t)o.hbm_budget_bytes);
+  auto cleanup = [&]() {
+    for (auto& L : s->slots) {
+      if (L.stream) hipStreamDestroy(L.stream);
+      if (L.ctl) hipFree(L.ctl);
+      if (L.host_err) hipHostFree(L.host_err);
+      if (L.done) hipEventDestroy(L.done);
+    }
+    for (hipStream_t c : s->copy_streams) hipStreamDestroy(c);
+    if (s->pin_base) hipHostFree(s->pin_base);
+    hipFree(s->dev_base);
+  };
+  if (o.copy_streams > 0) {
+    if (hipHostMalloc(&s->pin_base, (size_t)o.staging_bytes, hipHostMallocDefault) != hipSuccess) {
+      s->pin_base = nullptr;
+      cleanup();
+      return fail(WF_ENOMEM, "cannot allocate the server's pinned staging");
+    }
+    s->staging.reset((char*)s->pin_base, (size_t)o.staging_bytes);
+    for (int i = 0; i < o.copy_streams; ++i) {
+      hipStream_t c = nullptr;
+      if (hipStreamCreateWithFlags(&c, hipStreamNonBlocking) != hipSuccess) {
+        cleanup();
+        return fail(WF_EHIP, "cannot create a copy stream");
+      }
+      s->copy_streams.push_back(c);
+    }
+  }
   s->slots.resize((size_t)o.max_inflight);
   for (auto& L : s->slots) {
-    WF_HIP(hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
-    WF_HIP(hipMalloc(&L.ctl, CTL_WORDS * sizeof(uint32_t)));
-    WF_HIP(hipHostMalloc((void**)&L.host_err, sizeof(uint32_t), hipHostMallocDefault));
+    if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc(&L.ctl, CTL_WORDS * sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc((void**)&L.host_err, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) {
+      cleanup();
+      return fail(WF_EHIP, "cannot create the server's launch streams");
+    }
     *L.host_err = DEV_OK;
-    WF_HIP(hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
   }
   wf_server* raw = s.get();
   s->thread = std::thread([raw] { raw->run(); });
@@ -472,10 +638,12 @@ extern "C" wf_status wf_submit(wf_server* s, const wf_request* r, uint64_t* tick
   if (r->dtype != WF_F32 && r->dtype != WF_I32) return fail(WF_EINVAL, "unknown dtype");
   if (r->rule != WF_RULE_MIN && r->rule != WF_RULE_MAX) return fail(WF_EINVAL, "unknown rule");
   if (r->mode != WF_MODE_FULL && r->mode != WF_MODE_EDGES) return fail(WF_EINVAL, "unknown mode");
-  if (r->input_kind != WF_INPUT_DEVICE && r->input_kind != WF_INPUT_HOST)
+  if (r->input_kind != WF_INPUT_DEVICE && r->input_kind != WF_INPUT_HOST && r->input_kind != WF_INPUT_SEED &&
+      r->input_kind != WF_INPUT_HOST_PINNED)
     return fail(WF_EINVAL, "unknown input kind");
   const bool empty = r->m == 0 || r->n == 0;
-  if (!empty && (!r->input || r->ld_input < r->n)) return fail(WF_EINVAL, "input is NULL or ld_input < n");
+  if (!empty && r->input_kind != WF_INPUT_SEED && (!r->input || r->ld_input < r->n))
+    return fail(WF_EINVAL, "input is NULL or ld_input < n");
   if (r->n > ((int64_t)1 << 23) || (r->input_kind == WF_INPUT_DEVICE && r->ld_input > ((int64_t)1 << 23)))
     return fail(WF_EUNSUPPORTED, "n or ld_input above 2^23 is not supported");
   Req q;
@@ -484,6 +652,9 @@ extern "C" wf_status wf_submit(wf_server* s, const wf_request* r, uint64_t* tick
   if (!empty) {
     q.bytes = layout_of(*r).total;
     if (q.bytes > s->arena.size()) return fail(WF_E2BIG, "the request can never fit the server's memory budget");
+    if (r->input_kind == WF_INPUT_HOST && !s->copy_streams.empty() &&
+        (size_t)r->m * (size_t)r->n * 4 > s->staging.size())
+      return fail(WF_E2BIG, "the host input can never fit the server's pinned staging");
   }
   std::lock_guard<std::mutex> g(s->mu);
   if (s->stop) return fail(WF_ESHUTDOWN, "server is shutting down");
@@ -552,7 +723,8 @@ extern "C" wf_status wf_server_destroy(wf_server* s) {
     std::lock_guard<std::mutex> g(s->mu);
     s->stop = true;
     ++s->epoch;
-    // Requests not yet launched are cancelled; launched ones drain.
+    // Requests not yet launched are dropped; launched ones drain.  (wf_submit returns
+    // WF_ESHUTDOWN from here on; every ticket is invalid once this call returns.)
     for (uint64_t t : s->queue) s->reqs.erase(t);
     for (uint64_t t : s->admitted) s->reqs.erase(t);
     s->queue.clear();
@@ -561,6 +733,12 @@ extern "C" wf_status wf_server_destroy(wf_server* s) {
   }
   if (s->thread.joinable()) s->thread.join();
   set_device(s->ctx);
+  for (hipStream_t c : s->copy_streams) {
+    hipStreamSynchronize(c);
+    hipStreamDestroy(c);
+  }
+  for (auto& c : s->copying) hipEventDestroy(c.ev);
+  for (hipEvent_t e : s->event_pool) hipEventDestroy(e);
   for (auto& L : s->slots) {
     if (L.stream) {
       hipStreamSynchronize(L.stream);
@@ -575,7 +753,8 @@ extern "C" wf_status wf_server_destroy(wf_server* s) {
     if (L.host_err) hipHostFree(L.host_err);
     if (L.done) hipEventDestroy(L.done);
   }
-  s->arena.destroy();
+  if (s->pin_base) hipHostFree(s->pin_base);
+  if (s->dev_base) hipFree(s->dev_base);
   delete s;
   return WF_OK;
 }

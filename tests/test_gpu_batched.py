@@ -96,23 +96,38 @@ def test_mixed_dtype_batch_is_rejected():
 
 
 @pytest.mark.slow
-def test_benchmark_batch_sampled():
-    """The 4096-grid benchmark batch (sizes log-uniform in [64, 2048]) as the benchmark
-    launches it; 48 sampled grids compared with the oracle."""
+def test_benchmark_batch_every_grid_both_modes():
+    """The 4096-grid benchmark batch (sizes log-uniform in [64, 2048]) launched as the
+    benchmark launches it (autotuned, graph-replayed) in full mode, and again in edges
+    mode: every grid bit-exact against the fp32 oracle in both."""
+    from concurrent.futures import ThreadPoolExecutor
     shapes = wfgen.batch_shapes(4096)
     ds = []
     for g, (m, n) in enumerate(shapes):
         t = torch.empty((m, n), dtype=torch.float32, device=DEV)
         wfgen.fill_device(t, seed=wfgen.batch_seed(g))
         ds.append(t)
-    outs = wf.solve_batched(ds)
+    print("[batched] 4096 grids, full mode", flush=True)
+    full = wf.solve_batched(ds)
     torch.cuda.synchronize()
     wf.check()
-    rng = np.random.default_rng(3)
-    for g in sorted(rng.choice(len(shapes), 48, replace=False)):
+    print("[batched] 4096 grids, edges mode", flush=True)
+    edges = wf.solve_batched(ds, mode="edges")
+    torch.cuda.synchronize()
+    wf.check()
+
+    def check(g):
         m, n = shapes[g]
-        h = wfgen.cells(wfgen.batch_seed(g), m, n, "f32")
-        assert np.array_equal(_bits(outs[g]), _expect(h, "min", "f32")), (g, m, n)
+        exp = oracle.sweep(wfgen.cells(wfgen.batch_seed(g), m, n, "f32"), "min", "f32").view(np.uint32)
+        return (np.array_equal(_bits(full[g]), exp), np.array_equal(_bits(edges[g][0]), exp[-1]),
+                np.array_equal(_bits(edges[g][1]), exp[:, -1]), _bits(edges[g][2])[0] == exp[-1, -1])
+
+    bad = []
+    with ThreadPoolExecutor(12) as pool:
+        for g, ok in enumerate(pool.map(check, range(len(shapes)))):
+            if not all(ok):
+                bad.append((g, shapes[g], ok))
+    assert not bad, bad[:10]
 
 
 def test_three_waves_per_workgroup_is_rejected():
@@ -143,3 +158,43 @@ def test_graph_replay_after_single_solves_of_another_dtype():
         wf.check()
         for (m, n), h, o in zip(shapes, hs, outs):
             assert np.array_equal(_bits(o), _expect(h, "min", "f32")), (m, n, rep)
+
+
+def test_per_grid_path_on_several_streams():
+    """wf_solve_each: one launch per grid, spread over 1, 3 and 8 streams; every grid
+    bit-exact against the oracle, and more launches in flight than the context had
+    slots before."""
+    shapes, hs, ds = _batch(80, 1, 500, seed=17)
+    for S in (1, 3, 8):
+        print(f"[per-grid] {S} streams", flush=True)
+        streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(S - 1)]
+        plan = wf.EachPlan(ds)
+        for o in plan.outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.run(streams)
+        torch.cuda.synchronize()
+        wf.check()
+        for (m, n), h, o in zip(shapes, hs, plan.outs):
+            assert np.array_equal(_bits(o), _expect(h, "min", "f32")), (m, n, S)
+
+
+def test_replays_pipeline_and_follow_new_buffers():
+    """A graph-replayed plan run several times back to back without waiting (two lanes in
+    flight), then with the same shapes on new buffers: every run exact."""
+    shapes, hs, ds = _batch(24, 64, 400, seed=18)
+    outs = [torch.empty_like(d) for d in ds]
+    plan = wf.BatchPlan(ds, outs, waves_per_wg=1, order=2, use_graph=1)
+    for rep in range(4):
+        plan.run()
+    torch.cuda.synchronize()
+    wf.check()
+    for (m, n), h, o in zip(shapes, hs, outs):
+        assert np.array_equal(_bits(o), _expect(h, "min", "f32")), (m, n)
+    ds2 = [d.clone() for d in ds]
+    outs2 = [torch.full_like(d, float("nan")) for d in ds]
+    wf.BatchPlan(ds2, outs2, waves_per_wg=1, order=2, use_graph=1).run()
+    torch.cuda.synchronize()
+    wf.check()
+    for (m, n), h, o in zip(shapes, hs, outs2):
+        assert np.array_equal(_bits(o), _expect(h, "min", "f32")), (m, n)

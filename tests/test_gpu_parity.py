@@ -44,16 +44,16 @@ def _gamma_bound(H64):
     return k * U / (1 - k * U) * np.abs(H64)
 
 
-def _case(m, n, rule="min", dtype="f32", seed=1, explicit=False, ld_pad=0):
-    print(f"[parity] m={m} n={n} rule={rule} dtype={dtype} seed={seed} explicit={explicit} ld_pad={ld_pad}",
-          flush=True)
+def _case(m, n, rule="min", dtype="f32", seed=1, explicit=False, ld_pad=0, pad_value=0, waves_per_wg=0):
+    print(f"[parity] m={m} n={n} rule={rule} dtype={dtype} seed={seed} explicit={explicit} ld_pad={ld_pad} "
+          f"pad_value={pad_value} W={waves_per_wg}", flush=True)
     c = wfgen.cells(seed, m, n, dtype)
     top = left = None
     if explicit:
         top = (wfgen.vector(seed + 100, n + 1, dtype) * (3 if dtype == "f32" else 2)).astype(c.dtype)
         left = (wfgen.vector(seed + 200, m, dtype) * (3 if dtype == "f32" else 2)).astype(c.dtype)
     if ld_pad:
-        cb = np.zeros((m, n + ld_pad), c.dtype)
+        cb = np.full((m, n + ld_pad), pad_value, np.uint32).view(c.dtype)
         cb[:, :n] = c
         cd = _dev(cb)[:, :n]
         out = torch.full((m, n + ld_pad), float("nan") if dtype == "f32" else -7, dtype=cd.dtype, device=DEV)[:, :n]
@@ -61,7 +61,7 @@ def _case(m, n, rule="min", dtype="f32", seed=1, explicit=False, ld_pad=0):
         cd = _dev(c)
         out = torch.full((m, n), float("nan") if dtype == "f32" else -7, dtype=cd.dtype, device=DEV)
     H = wf.solve(cd, out=out, rule=rule, top=None if top is None else _dev(top),
-                 left=None if left is None else _dev(left))
+                 left=None if left is None else _dev(left), waves_per_wg=waves_per_wg)
     got = _host(H)
     wf.check()
     if dtype == "f32":
@@ -117,6 +117,23 @@ def test_leading_dimension(m, n):
     _case(m, n, seed=7, ld_pad=13)
 
 
+@pytest.mark.parametrize("m,n", [(65, 65), (300, 513), (130, 1000)])
+@pytest.mark.parametrize("dtype", ["f32", "i32"])
+def test_row_padding_holding_the_sentinel(m, n, dtype):
+    """Row padding (ld_cost > n) that holds the handoff sentinel's bit pattern (0xFFFFFFFF
+    for fp32, INT32_MIN for int32) must neither change a cell nor stall a band."""
+    pad = 0xFFFFFFFF if dtype == "f32" else 0x80000000
+    _case(m, n, dtype=dtype, seed=9, ld_pad=5, pad_value=pad)
+    _case(m, n, rule="max", dtype=dtype, seed=9, ld_pad=5, pad_value=pad, waves_per_wg=2)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (65, 65), (129, 300), (300, 513), (2100, 333), (1024, 1024)])
+@pytest.mark.parametrize("rule", ["min", "max"])
+def test_two_compute_waves_per_workgroup(m, n, rule):
+    """wf_solve_tuned with bands of 128 rows: two compute waves chained through LDS."""
+    _case(m, n, rule=rule, seed=10, waves_per_wg=2)
+
+
 def test_config_small_grid_1024_and_repeatability():
     """The 1024 x 1024 configuration, twice, bit-identical both times."""
     a = _case(1024, 1024, seed=1)
@@ -164,11 +181,13 @@ def test_full_size_16384_against_fp32_oracle():
     exp = oracle.sweep(c, "min", "f32")
     bad = np.count_nonzero(got.view(np.uint32) != exp.view(np.uint32))
     assert bad == 0, f"{bad} cells differ"
-    rows = [0, 1, n // 2, m - 2, m - 1] + list(np.random.default_rng(2).integers(0, m, 16))
-    exp64 = oracle.sweep(c, "min", "f64")
+    # fp64 bound on rows 0, 1, n/2, n-2, n-1 and 64 seeded random rows (final cell included)
+    rows = [0, 1, n // 2, m - 2, m - 1] + [int(r) for r in np.random.default_rng(2).choice(m, 64, replace=False)]
+    del exp
+    _, _, want = oracle.sweep_banded(lambda r0, k: c[r0:r0 + k], m, n, "min", "f64", band=2048, want_rows=rows)
     for r in rows:
         k = (r + np.arange(n) + 1).astype(np.float64)
-        assert (np.abs(got[r].astype(np.float64) - exp64[r]) <= k * U / (1 - k * U) * exp64[r]).all()
+        assert (np.abs(got[r].astype(np.float64) - want[r]) <= k * U / (1 - k * U) * want[r]).all(), r
 
 
 @pytest.mark.slow
@@ -187,7 +206,30 @@ def test_full_size_65536_edges_against_fp32_oracle():
     def rows(row0, nrows):
         return cd[row0:row0 + nrows].cpu().numpy()
 
-    exp_lr, exp_lc, _ = oracle.sweep_banded(rows, m, n, "min", "f32", band=2048)
-    assert np.array_equal(got_lr.view(np.uint32), exp_lr.view(np.uint32))
-    assert np.array_equal(got_lc.view(np.uint32), exp_lc.view(np.uint32))
-    assert got_fc.view(np.uint32)[0] == exp_lr.view(np.uint32)[-1]
+    # fp32 (bit-exact) and fp64 (rounding bound) oracles band by band, on two threads over
+    # the same host copy of each band (the oracle's C loop runs without the GIL).
+    from concurrent.futures import ThreadPoolExecutor
+    band = 2048
+    last32 = last64 = None
+    lc32 = np.empty(m, np.float32)
+    lc64 = np.empty(m, np.float64)
+    with ThreadPoolExecutor(2) as pool:
+        for row0 in range(0, m, band):
+            cb = rows(row0, band)
+            t32 = None if last32 is None else np.concatenate([[np.inf], last32]).astype(np.float32)
+            t64 = None if last64 is None else np.concatenate([[np.inf], last64])
+            l32 = np.full(band, np.inf, np.float32)
+            l64 = np.full(band, np.inf)
+            f32 = pool.submit(oracle.sweep, cb, "min", "f32", t32, l32, False)
+            f64 = pool.submit(oracle.sweep, cb, "min", "f64", t64, l64, False)
+            (last32, c32), (last64, c64) = f32.result(), f64.result()
+            lc32[row0:row0 + band], lc64[row0:row0 + band] = c32, c64
+    assert np.array_equal(got_lr.view(np.uint32), last32.view(np.uint32))
+    assert np.array_equal(got_lc.view(np.uint32), lc32.view(np.uint32))
+    assert got_fc.view(np.uint32)[0] == last32.view(np.uint32)[-1]
+    j = np.arange(n, dtype=np.float64)
+    k = (m - 1) + j + 1
+    assert (np.abs(got_lr.astype(np.float64) - last64) <= k * U / (1 - k * U) * last64).all()
+    i = np.arange(m, dtype=np.float64)
+    k = i + (n - 1) + 1
+    assert (np.abs(got_lc.astype(np.float64) - lc64) <= k * U / (1 - k * U) * lc64).all()

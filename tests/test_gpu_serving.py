@@ -86,14 +86,84 @@ def test_mix_equals_alone():
     _sync()
 
 
-def test_served_result_matches_oracle():
-    c = wfgen.cells(61, 300, 513, "f32")
+def test_served_results_match_oracle_and_alone_at_scale():
+    """250 requests of the serving mix's shape (square, n log-uniform, smaller here so the
+    oracle keeps up) submitted in a burst through a small budget, so admission, batching
+    and overlapping launches all happen: all 250 bit-equal to the grid swept alone, 25 of
+    them to the fp32 oracle as well."""
+    reqs = wfgen.serving_requests(250, rate_per_s=1.0, lo=64, hi=700, seed=55)
+    grids = [wfgen.cells(seed, n, n, "f32") for (_, n, seed) in reqs]
+    devs = [torch.from_numpy(g).to(DEV) for g in grids]
+    _sync()
+    print(f"[serving] {len(reqs)} requests", flush=True)
+    with wf.Server(budget_bytes=96 << 20, max_inflight=4, max_batch=32) as srv:
+        tickets = [srv.submit(d) for d in devs]
+        res = _wait_all(srv, tickets, timeout_s=120)
+        for q, (t, d) in enumerate(zip(tickets, devs)):
+            alone = wf.solve(d)
+            assert np.array_equal(_bits(res[t]["out"]), _bits(alone)), q
+            if q % 10 == 0:
+                assert np.array_equal(_bits(res[t]["out"]), oracle.sweep(grids[q], "min", "f32").view(np.uint32)), q
+            srv.release(t)
+        assert srv.memory()[0] == 0
+
+
+def test_host_inputs_on_copy_streams():
+    """Host inputs (pageable numpy and pinned CPU tensors) copied at admission on two copy
+    streams, overlapping earlier launches: results equal the oracle."""
+    specs = [(int(m), int(n)) for m, n in np.random.default_rng(8).integers(1, 600, size=(30, 2))]
+    cs = [wfgen.cells(80 + q, m, n, "f32") for q, (m, n) in enumerate(specs)]
+    print("[serving] copy streams", flush=True)
+    with wf.Server(budget_bytes=256 << 20, max_inflight=3, max_batch=4, copy_streams=2,
+                   staging_bytes=8 << 20) as srv:
+        tickets = []
+        for q, c in enumerate(cs):
+            x = c if q % 2 == 0 else torch.from_numpy(c).pin_memory()
+            tickets.append(srv.submit(x, mode="full" if q % 3 else "edges"))
+        res = _wait_all(srv, tickets)
+        for q, (t, c) in enumerate(zip(tickets, cs)):
+            exp = oracle.sweep(c, "min", "f32").view(np.uint32)
+            if q % 3:
+                assert np.array_equal(_bits(res[t]["out"]), exp), q
+            assert np.array_equal(_bits(res[t]["last_row"]), exp[-1]), q
+            assert np.array_equal(_bits(res[t]["last_col"]), exp[:, -1]), q
+            srv.release(t)
+
+
+def test_seeded_requests_match_generator_and_oracle():
+    """WF_INPUT_SEED: the server generates the inputs on the device; results equal the
+    oracle on the host generator's grid (f32 and i32)."""
+    print("[serving] seeded", flush=True)
     with wf.Server(budget_bytes=64 << 20) as srv:
-        t = srv.submit(c)  # host input, copied in at admission
+        specs = [(300, 513, 91, "f32", "min"), (65, 7, 92, "i32", "max"), (129, 200, 93, "f32", "max")]
+        tickets = [srv.submit_seeded(m, n, seed, dt, rule) for (m, n, seed, dt, rule) in specs]
+        res = _wait_all(srv, tickets)
+        for (m, n, seed, dt, rule), t in zip(specs, tickets):
+            c = wfgen.cells(seed, m, n, dt)
+            exp = oracle.sweep(c, rule, "f32").view(np.uint32) if dt == "f32" else \
+                oracle.sweep(c, rule, "i64").astype(np.int32)
+            assert np.array_equal(_bits(res[t]["out"]), exp), (m, n, dt, rule)
+            srv.release(t)
+
+
+def test_device_input_written_asynchronously_before_submit():
+    """A device input still being written on the caller's stream when it is submitted:
+    the launch waits for it on the device (ready event), with no host synchronization."""
+    m = n = 1500
+    exp = oracle.sweep(wfgen.cells(94, m, n, "f32"), "min", "f32").view(np.uint32)
+    print("[serving] ready event", flush=True)
+    with wf.Server(budget_bytes=128 << 20) as srv:
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            x = torch.zeros((m, n), dtype=torch.float32, device=DEV)
+            for _ in range(20):  # keep the stream busy so the fill lands late
+                x.add_(1.0)
+            wfgen.fill_device(x, seed=94, stream=side)
+            t = srv.submit(x)  # records the ready event on `side`, the current stream here
         r = _wait_all(srv, [t])[t]
         got = _bits(r["out"])
         srv.release(t)
-    assert np.array_equal(got, oracle.sweep(c, "min", "f32").view(np.uint32))
+    assert np.array_equal(got, exp)
 
 
 def test_budget_limits_admission():
