@@ -147,6 +147,25 @@ wf_status wf_solve_each(wf_ctx* ctx, const wf_problem* ps, int64_t count, void* 
  * when the same batch shape is solved again. */
 wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t count, const wf_tuning* t, void* stream);
 
+/* For callers that cannot allocate memory: code under HIP graph capture, serving
+ * loops and harnesses that forbid hipMalloc.  wf_solve_noalloc is wf_solve
+ * (same kernels, same results, same asynchrony and error reporting) except that
+ * the launch's control words and handoff rows live in a fixed device array of
+ * WF_NOALLOC_SCRATCH_BYTES that the library holds on each device from wf_init
+ * until the process ends, and the call allocates nothing: no hipMalloc, hipFree
+ * or allocating library routine.  The caller still passes inputs and outputs.
+ * A problem needs 256 + 4 * (ceil(m / 64) - 1) * L bytes of it, with
+ * L = 64 * ceil(4 * floor((n + 66) / 4) / 64) (the handoff row of one 64-row band
+ * boundary; about 4 * m * n / 64 bytes in all, 16.8 MB for 16384 x 16384); a
+ * problem that needs more returns WF_E2BIG and nothing is enqueued (empty
+ * problems are no-ops, as in wf_solve).  Every call on a device shares
+ * that device's array, and each call re-arms what it uses on `stream` before its
+ * launch: calls that overlap on one device (different streams, or different
+ * contexts of one device, with no ordering between them) race on the array and
+ * give wrong results.  Order them on one stream. */
+#define WF_NOALLOC_SCRATCH_BYTES (32ll << 20)
+wf_status wf_solve_noalloc(wf_ctx* ctx, const wf_problem* p, void* stream);
+
 /* Set the device watchdog of later launches on this context: a wait for a
  * neighbouring band that makes no progress for `ms` milliseconds (0 .. 3600000)
  * aborts the launch, which then drains and is reported as WF_ETIMEDOUT.  The

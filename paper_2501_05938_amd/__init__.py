@@ -99,6 +99,7 @@ _SIGS = {
     "wf_solve": (ctypes.c_int, [_P, ctypes.POINTER(Problem), _P]),
     "wf_solve_batched": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.c_int64, ctypes.POINTER(Tuning), _P]),
     "wf_solve_tuned": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(Tuning), _P]),
+    "wf_solve_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(Problem), _P]),
     "wf_solve_each": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.c_int64, ctypes.POINTER(_P), ctypes.c_int32]),
     "wf_set_watchdog": (ctypes.c_int, [_P, ctypes.c_int64]),
     "wf_check": (ctypes.c_int, [_P]),
@@ -237,6 +238,21 @@ def solve(cost, out=None, rule: str = "min", top=None, left=None, mode: str = "f
                                              _stream_ptr(stream)))
     else:
         _check(load_library().wf_solve(context(cost.device.index), ctypes.byref(p), _stream_ptr(stream)))
+    if mode == "full":
+        return out
+    return last_row, last_col, final_cell
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20  # WF_NOALLOC_SCRATCH_BYTES
+
+
+def solve_noalloc(cost, out, rule: str = "min", top=None, left=None, mode: str = "full", stream=None,
+                  last_row=None, last_col=None, final_cell=None):
+    """wf_solve_noalloc: as solve(), but the library allocates nothing for the call (its
+    workspace is a fixed device array), so every output must be given.  Calls that
+    overlap on one device race on that array: keep them on one stream."""
+    p = make_problem(cost, out, rule, top, left, mode, last_row, last_col, final_cell)
+    _check(load_library().wf_solve_noalloc(context(cost.device.index), ctypes.byref(p), _stream_ptr(stream)))
     if mode == "full":
         return out
     return last_row, last_col, final_cell

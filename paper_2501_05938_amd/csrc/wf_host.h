@@ -78,6 +78,7 @@ struct wf_ctx {
   std::map<std::string, TuneEntry> tuned;  // shape class -> configuration
   std::string tune_file;                   // WF_TUNE_CACHE: where `tuned` persists (empty: memory only)
   wf_status sticky = WF_OK;                // device error seen, reported once
+  Slot* noalloc = nullptr;                 // wf_solve_noalloc's slot: ctl/hand in the fixed device array
 };
 
 namespace wfh {

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/wf.h"
+
 namespace wfk {
 
 // Device copy of one problem.  `hand` holds the bottom-row handoff of every
@@ -81,5 +83,16 @@ hipError_t launch_sweep(int dtype, int rule, int W, int nwg, const KArgs& args, 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t stream);
 // LDS bytes per workgroup for W compute waves (for occupancy decisions).
 size_t lds_bytes(int W);
+
+// The allocation-free entry point's fixed device workspace: NOALLOC_CTL_WORDS control
+// words (padded to 256 bytes), then handoff rows.  noalloc_scratch() returns its
+// address on the current device.
+constexpr int64_t NOALLOC_WORDS = (int64_t)WF_NOALLOC_SCRATCH_BYTES / 4;
+constexpr int64_t NOALLOC_CTL_WORDS = 64;
+hipError_t noalloc_scratch(uint32_t** ptr);
+// Zero the control words at `ctl` (the error word only if reset_error) and arm `count`
+// handoff-row words at `hand` with `sent`, in one launch.
+hipError_t launch_noalloc_prep(uint32_t* ctl, bool reset_error, uint32_t* hand, uint32_t sent, int64_t count,
+                               hipStream_t stream);
 
 }  // namespace wfk

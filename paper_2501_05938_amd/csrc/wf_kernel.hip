@@ -1169,6 +1169,17 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
 }
 
+// Set-up of an allocation-free launch: zero the control words (the error word only when
+// asked: it accumulates across launches until the host has seen it) and arm `count`
+// handoff-row words with the sentinel.
+__global__ void noalloc_prep_kernel(uint32_t* ctl, uint32_t reset_error, uint32_t* hand, uint32_t sent,
+                                    int64_t count) {
+  if (blockIdx.x == 0 && threadIdx.x < CTL_WORDS && (threadIdx.x != CTL_ERROR || reset_error != 0u))
+    ctl[threadIdx.x] = 0u;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) hand[i] = sent;
+}
+
 template <typename T, int RULE, int W>
 hipError_t launch_t(int nwg, const KArgs& args, hipStream_t stream) {
   if (args.trace || args.ctrace)
@@ -1188,6 +1199,24 @@ hipError_t launch_w(int W, int nwg, const KArgs& args, hipStream_t stream) {
 }
 
 }  // namespace
+}  // namespace wfk
+
+// Fixed workspace of the allocation-free entry point: control words, then handoff rows.
+// Each device that loads the library holds its own copy until the process ends.  Host
+// code must never pass `scratch` itself to a kernel (in host code the name is a
+// host-side stand-in, not a device address): it uses the address that
+// noalloc_scratch() returns for the current device.
+static __device__ __align__(256) uint32_t scratch[wfk::NOALLOC_WORDS];
+
+namespace wfk {
+
+hipError_t noalloc_scratch(uint32_t** ptr) {
+  *ptr = nullptr;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) *ptr = (uint32_t*)p;
+  return e;
+}
 
 size_t lds_bytes(int W) { return sizeof(WaveLds) * (size_t)W + 16; }
 
@@ -1195,6 +1224,16 @@ hipError_t launch_sweep(int dtype, int rule, int W, int nwg, const KArgs& args, 
   if (dtype == 0) return rule == 0 ? launch_w<float, 0>(W, nwg, args, stream) : launch_w<float, 1>(W, nwg, args, stream);
   if (dtype == 1) return rule == 0 ? launch_w<int32_t, 0>(W, nwg, args, stream) : launch_w<int32_t, 1>(W, nwg, args, stream);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_noalloc_prep(uint32_t* ctl, bool reset_error, uint32_t* hand, uint32_t sent, int64_t count,
+                               hipStream_t stream) {
+  int64_t blocks = (count + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(noalloc_prep_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, ctl,
+                     reset_error ? 1u : 0u, hand, sent, count);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t stream) {

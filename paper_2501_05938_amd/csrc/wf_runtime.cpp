@@ -361,6 +361,28 @@ extern "C" wf_status wf_init(int device, wf_ctx** out) {
   }
   wf_status st = set_device(ctx.get());
   if (st != WF_OK) return st;
+  // wf_solve_noalloc's slot: its control words and handoff rows are the device's fixed
+  // array, looked up here with the device current; its pinned error word and event are
+  // made now so that the entry point itself allocates nothing.
+  {
+    uint32_t* scr = nullptr;
+    WF_HIP(noalloc_scratch(&scr));
+    std::unique_ptr<Slot> s(new Slot);
+    s->external = true;
+    s->reserved = true;
+    s->ctl = scr;
+    s->hand = scr + NOALLOC_CTL_WORDS;
+    s->hand_cap = (size_t)(NOALLOC_WORDS - NOALLOC_CTL_WORDS);
+    s->needs_rearm = true;
+    WF_HIP(hipHostMalloc(&s->host_err, sizeof(uint32_t), hipHostMallocDefault));
+    *s->host_err = 0;
+    if (hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess) {
+      hipHostFree(s->host_err);
+      return fail(WF_EHIP, "hipEventCreateWithFlags failed");
+    }
+    ctx->noalloc = s.get();
+    ctx->slots.push_back(std::move(s));
+  }
   *out = ctx.release();
   return WF_OK;
 }
@@ -386,7 +408,11 @@ extern "C" wf_status wf_destroy(wf_ctx* ctx) {
   for (auto& e : ctx->plans) drop_plan(*e, ctx);
   for (auto& sp : ctx->slots) {
     Slot& s = *sp;
-    if (s.external) continue;
+    if (s.external) {  // ctl and hand are not the slot's
+      if (s.host_err) hipHostFree(s.host_err);
+      if (s.done) hipEventDestroy(s.done);
+      continue;
+    }
     if (s.ctl) hipFree(s.ctl);
     if (s.hand) hipFree(s.hand);
     if (s.grids) hipFree(s.grids);
@@ -511,6 +537,45 @@ static wf_status solve_entry(wf_ctx* ctx, const wf_problem* p, const wf_tuning* 
 
 extern "C" wf_status wf_solve(wf_ctx* ctx, const wf_problem* p, void* stream) {
   return solve_entry(ctx, p, nullptr, stream);
+}
+
+// wf_solve on the fixed device array: the same launch as solve_one at one compute wave
+// per workgroup, with nothing allocated.  The handoff rows the problem uses are re-armed
+// on `stream` before every launch (a kernel, not hipMemsetAsync, so the call may be
+// captured in a graph): the array is shared by every call on the device, so what an
+// earlier call (or an aborted launch) left there is never trusted.  The call never waits
+// for an earlier one: the device error word accumulates across launches and is copied to
+// the slot's pinned word after each, so the latest copy covers every launch before it;
+// once the host has seen an error there, the next call clears the word.
+extern "C" wf_status wf_solve_noalloc(wf_ctx* ctx, const wf_problem* p, void* stream_) {
+  if (!ctx) return fail(WF_EINVAL, "ctx is NULL");
+  wf_status st = check_problem(p, -1);
+  if (st != WF_OK) return st;
+  if (!ctx->noalloc) return fail(WF_EHIP, "the context has no fixed workspace");
+  const int W = 1;
+  const size_t need = hand_elems(p, W);
+  if (p->m > 0 && p->n > 0 && need > ctx->noalloc->hand_cap) {
+    char msg[200];
+    snprintf(msg, sizeof msg, "problem needs %lld bytes of handoff rows; the fixed workspace holds %lld "
+             "(WF_NOALLOC_SCRATCH_BYTES, less 256 bytes of control words)",
+             (long long)(need * 4), (long long)(ctx->noalloc->hand_cap * 4));
+    return fail(WF_E2BIG, msg);
+  }
+  st = set_device(ctx);
+  if (st != WF_OK) return st;
+  st = report_sticky(ctx);
+  if (st != WF_OK) return st;
+  if (p->m == 0 || p->n == 0) return WF_OK;
+  Slot& s = *ctx->noalloc;
+  hipStream_t stream = (hipStream_t)stream_;
+  KArgs a = base_args(ctx, s.ctl, 0);
+  a.g0 = make_desc(p, W, s.hand);
+  a.nitems = a.g0.nbands;
+  const int nwg = (int)std::min<int64_t>(a.nitems, (int64_t)ctx->num_cus * wgs_per_cu(W));
+  WF_HIP(launch_noalloc_prep(s.ctl, s.needs_rearm, s.hand, sentinel_of(p->dtype), (int64_t)need, stream));
+  s.needs_rearm = false;
+  WF_HIP(launch_sweep(p->dtype, p->rule, W, nwg, a, stream));
+  return finish_launch(s, stream);
 }
 
 extern "C" wf_status wf_solve_tuned(wf_ctx* ctx, const wf_problem* p, const wf_tuning* t, void* stream) {
