@@ -431,6 +431,9 @@ def serving(torch, wf, wfgen, grids, requests, warmup, load, inflight=4, batch=2
                 q, g, t_arr = outstanding.pop(tk)
                 if isinstance(r, dict):
                     sampled[q] = (g, r["out"].clone())
+                    # the copy runs on torch's stream: it must be done before the server may
+                    # hand the released memory to a later request
+                    torch.cuda.current_stream().synchronize()
                 srv.release(tk)
                 if q >= warmup:
                     lat.append(t_obs - t_arr)

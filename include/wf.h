@@ -107,7 +107,10 @@ typedef struct wf_tuning {
   int32_t order;           /* batched work order: 0 = automatic, 1 = grid-major, 2 = interleaved by band */
   int32_t use_graph;       /* batched: 1 = capture and replay a hipGraph, 0 = plain launch,
                               -1 = plain launch without autotuning */
-  int32_t reserved[4];     /* must be 0 */
+  int32_t rows_per_lane;   /* grid rows each lane of a compute wave owns: 1 or 2 (0 = automatic);
+                              bands are 64 * waves_per_wg * rows_per_lane rows; two waves of two
+                              rows per lane are not offered (WF_EUNSUPPORTED) */
+  int32_t reserved[3];     /* must be 0 */
 } wf_tuning;
 
 typedef struct wf_ctx wf_ctx;
@@ -121,9 +124,12 @@ wf_status wf_destroy(wf_ctx* ctx);
 /* Sweep one grid with one persistent kernel launch on `stream`. */
 wf_status wf_solve(wf_ctx* ctx, const wf_problem* p, void* stream);
 
-/* wf_solve with explicit tuning (NULL: as wf_solve): waves_per_wg picks bands of 64 or
- * 128 rows (two compute waves chained through LDS), max_wgs caps the persistent
- * workgroups; order and use_graph are ignored. */
+/* wf_solve with explicit tuning (NULL: as wf_solve): waves_per_wg and rows_per_lane pick
+ * the band shape -- 64-row bands (1, 1), 128-row bands of two compute waves chained
+ * through LDS (2, 1) or of one wave whose lanes own two rows each (1, 2); wf_solve takes
+ * (1, 1) -- and max_wgs caps the
+ * persistent workgroups; order and use_graph are ignored.  Every shape gives the same,
+ * bit-identical result. */
 wf_status wf_solve_tuned(wf_ctx* ctx, const wf_problem* p, const wf_tuning* t, void* stream);
 
 /* The per-grid path: every problem swept by its own launch (as wf_solve), problem i
@@ -137,12 +143,14 @@ wf_status wf_solve_each(wf_ctx* ctx, const wf_problem* ps, int64_t count, void* 
  * `stream`; the bands of all grids are packed into one work list so the thin
  * first and last diagonals of one grid overlap the wide middle of another.
  * All grids of one call share dtype and rule (WF_EUNSUPPORTED otherwise).
- * Autotuning: when `t` is NULL or leaves both waves_per_wg and order at 0 (and
- * use_graph is not -1), the first call for a batch shape (count, sizes, dtype,
- * rule, mode) runs the batch twice per candidate configuration (waves per
- * workgroup 1, 2 x grid-major / interleaved order), synchronously, timing the
- * second run on `stream`, and keeps the fastest in the context's tuning table; later
- * calls with that shape use it.  Every trial writes the full, correct result.
+ * Autotuning: when `t` is NULL or leaves waves_per_wg, rows_per_lane and order at 0
+ * (and use_graph is not -1), the first call for a batch of a new shape class (dtype,
+ * rule, modes, and the binary magnitudes of the grid count, total cells, tallest and
+ * widest grid) runs the batch twice per candidate configuration (the three band
+ * shapes x grid-major / interleaved order x all or half of the resident workgroups),
+ * synchronously, timing the second run on `stream`, and keeps the fastest in the
+ * context's tuning table (persisted to the JSON file WF_TUNE_CACHE names, if set);
+ * later calls of that class use it.  Every trial writes the full, correct result.
  * With use_graph = 1 the chosen launch is captured in a hipGraph and replayed
  * when the same batch shape is solved again. */
 wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t count, const wf_tuning* t, void* stream);
@@ -154,8 +162,9 @@ wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t count, con
  * WF_NOALLOC_SCRATCH_BYTES that the library holds on each device from wf_init
  * until the process ends, and the call allocates nothing: no hipMalloc, hipFree
  * or allocating library routine.  The caller still passes inputs and outputs.
- * A problem needs 256 + 4 * (ceil(m / 64) - 1) * L bytes of it, with
- * L = 64 * ceil(4 * floor((n + 66) / 4) / 64) (the handoff row of one 64-row band
+ * It uses the band shape wf_solve picks (bands of 64 rows), and a problem needs
+ * 256 + 4 * (ceil(m / 64) - 1) * L bytes of it, with
+ * L = 64 * ceil(4 * floor((n + 66) / 4) / 64) (the handoff row of one band
  * boundary; about 4 * m * n / 64 bytes in all, 16.8 MB for 16384 x 16384); a
  * problem that needs more returns WF_E2BIG and nothing is enqueued (empty
  * problems are no-ops, as in wf_solve).  Every call on a device shares

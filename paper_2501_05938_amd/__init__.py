@@ -48,7 +48,7 @@ class Problem(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("waves_per_wg", ctypes.c_int32), ("max_wgs", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("use_graph", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -211,7 +211,8 @@ def make_problem(cost, out=None, rule="min", top=None, left=None, mode="full",
 
 
 def solve(cost, out=None, rule: str = "min", top=None, left=None, mode: str = "full", stream=None,
-          last_row=None, last_col=None, final_cell=None, waves_per_wg: int = 0, max_wgs: int = 0):
+          last_row=None, last_col=None, final_cell=None, waves_per_wg: int = 0, max_wgs: int = 0,
+          rows_per_lane: int = 0):
     """Sweep one grid on the GPU (asynchronous on `stream`, default: current stream).
 
     mode="full": returns H (m x n), written into `out` if given.
@@ -231,9 +232,9 @@ def solve(cost, out=None, rule: str = "min", top=None, left=None, mode: str = "f
         if final_cell is None:
             final_cell = torch.empty(1, dtype=cost.dtype, device=cost.device)
     p = make_problem(cost, out, rule, top, left, mode, last_row, last_col, final_cell)
-    if waves_per_wg or max_wgs:
+    if waves_per_wg or max_wgs or rows_per_lane:
         t = Tuning()
-        t.waves_per_wg, t.max_wgs = waves_per_wg, max_wgs
+        t.waves_per_wg, t.max_wgs, t.rows_per_lane = waves_per_wg, max_wgs, rows_per_lane
         _check(load_library().wf_solve_tuned(context(cost.device.index), ctypes.byref(p), ctypes.byref(t),
                                              _stream_ptr(stream)))
     else:
@@ -268,7 +269,8 @@ class BatchPlan:
     """
 
     def __init__(self, costs, outs=None, rule: str = "min", mode: str = "full",
-                 waves_per_wg: int = 0, max_wgs: int = 0, order: int = 0, use_graph: int = 1):
+                 waves_per_wg: int = 0, max_wgs: int = 0, order: int = 0, use_graph: int = 1,
+                 rows_per_lane: int = 0):
         import torch
         if outs is None:
             outs = []
@@ -289,6 +291,7 @@ class BatchPlan:
                 arr[i] = make_problem(c, None, rule, mode=mode, last_row=lr, last_col=lc, final_cell=fc)
         t = Tuning()
         t.waves_per_wg, t.max_wgs, t.order, t.use_graph = waves_per_wg, max_wgs, order, use_graph
+        t.rows_per_lane = rows_per_lane
         self.costs, self.outs = list(costs), outs
         self._arr, self._tuning = arr, t
         self._device = costs[0].device.index if costs else None
@@ -327,10 +330,11 @@ def set_watchdog(ms: int, device: int | None = None):
 
 
 def solve_batched(costs, outs=None, rule: str = "min", mode: str = "full", stream=None,
-                  waves_per_wg: int = 0, max_wgs: int = 0, order: int = 0, use_graph: int = 1):
+                  waves_per_wg: int = 0, max_wgs: int = 0, order: int = 0, use_graph: int = 1,
+                  rows_per_lane: int = 0):
     """Sweep many independent grids in one persistent launch.  Returns the list of outputs
     (H per grid in full mode, (last_row, last_col, final_cell) in edges mode)."""
-    return BatchPlan(costs, outs, rule, mode, waves_per_wg, max_wgs, order, use_graph).run(stream)
+    return BatchPlan(costs, outs, rule, mode, waves_per_wg, max_wgs, order, use_graph, rows_per_lane).run(stream)
 
 
 def check(device: int | None = None):
@@ -356,7 +360,7 @@ class Server:
         srv = Server(budget_bytes=8 << 30)
         t = srv.submit(cost)                  # device tensor (kept alive until done) or host array
         r = srv.poll(t)                       # None while pending
-        H = r["out"]                          # torch view of server memory; copy before release
+        H = r["out"].clone()                  # server memory: copy it, and let the copy finish, before release
         srv.release(t)
     """
 

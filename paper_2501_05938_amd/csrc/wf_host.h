@@ -40,7 +40,7 @@ struct BatchPlanEntry {
   uint64_t hash = 0;
   std::vector<wf_problem> probs;          // the problem array last launched through this plan
   std::vector<int64_t> shape;             // (m, n, mode) per problem: what the plan depends on
-  int W = 1, order = 1, nwg = 0, dtype = 0, rule = 0;
+  int bs = 1, order = 1, nwg = 0, dtype = 0, rule = 0;
   bool use_graph = false;
   std::vector<int64_t> perm;              // problem index of descriptor k
   std::vector<wfk::Item> items;
@@ -60,7 +60,7 @@ struct BatchPlanEntry {
 };
 
 struct TuneEntry {
-  int W = 1, order = 1, wgs = 0;
+  int bs = 1, order = 1, wgs = 0;  // band shape (wfh::shape_*), work order, workgroups
   double ms = 0;
 };
 
@@ -89,16 +89,25 @@ wf_status fail(wf_status s, const std::string& msg);
 wf_status set_device(wf_ctx* ctx);
 // Validate one problem (idx >= 0 names it in the message).
 wf_status check_problem(const wf_problem* p, int64_t idx);
-// Compute waves per workgroup for a single grid with m rows.
-int choose_waves(int64_t m);
-// Resident workgroups per compute unit at W compute waves per workgroup.
-int wgs_per_cu(int W);
+// Band shapes: 1 = one compute wave with one row per lane (64-row bands); 2 = two
+// compute waves chained through LDS (128-row bands); 3 = one compute wave with two rows
+// per lane (128-row bands).
+constexpr int SHAPE_MAX = 3;
+inline int shape_waves(int bs) { return bs == 2 ? 2 : 1; }
+inline int shape_rows_per_lane(int bs) { return bs == 3 ? 2 : 1; }
+inline int shape_rows(int bs) { return 64 * shape_waves(bs) * shape_rows_per_lane(bs); }
+// Band shape for a single grid with m rows.
+int choose_shape(int64_t m);
+// Resident workgroups per compute unit at band shape bs.
+int wgs_per_cu(int bs);
+// Launch of the sweep kernel at band shape bs.
+hipError_t launch_shape(int dtype, int rule, int bs, int nwg, const wfk::KArgs& args, hipStream_t stream);
 // Handoff sentinel of a dtype.
 uint32_t sentinel_of(int dtype);
-// Kernel descriptor of a problem, cut into bands of 64*W rows.
-wfk::GridDesc make_desc(const wf_problem* p, int W, uint32_t* hand);
-// Handoff-row elements a problem needs at W.
-size_t hand_elems(const wf_problem* p, int W);
+// Kernel descriptor of a problem, cut into bands of shape bs.
+wfk::GridDesc make_desc(const wf_problem* p, int bs, uint32_t* hand);
+// Handoff-row elements a problem needs at band shape bs.
+size_t hand_elems(const wf_problem* p, int bs);
 // Arguments of a launch over `nitems` work items with the context's watchdog and fault hook.
 // (Consumes the context's one-shot fault hook.)
 wfk::KArgs base_args(wf_ctx* ctx, uint32_t* ctl, int64_t nitems);

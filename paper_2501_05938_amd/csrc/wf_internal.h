@@ -69,20 +69,19 @@ enum { DEV_OK = 0, DEV_TIMEOUT = 1 };
 constexpr uint32_t SENT_F32 = 0xFFFFFFFFu;
 constexpr uint32_t SENT_I32 = 0x80000000u;
 
-// Rows per compute wave and positions per handoff row slack.
-constexpr int ROWS_PER_WAVE = 64;
-
-// Number of groups of 4 steps a 64-row strip of an n-column grid takes.
-__host__ __device__ inline int64_t groups_for(int64_t n) { return (n + 63 + 3) / 4; }
-// Handoff row length in positions (>= 4 * groups_for(n)).
-__host__ __device__ inline int64_t hand_ld_for(int64_t n) { return ((4 * groups_for(n)) + 63) / 64 * 64; }
+// Number of groups of 4 steps the walk of a strip of 64 R rows (R rows per lane) of an
+// n-column grid takes: its last row finishes column n-1 at step n + 64 R - 2.
+__host__ __device__ inline int64_t groups_for(int64_t n, int R) { return (n + 64 * R - 1 + 3) / 4; }
+// Handoff row length in positions (>= 4 * groups_for(n, R)).
+__host__ __device__ inline int64_t hand_ld_for(int64_t n, int R) { return ((4 * groups_for(n, R)) + 63) / 64 * 64; }
 
 // Launch helpers implemented in wf_kernel.hip.
-// dtype 0 = f32, 1 = i32; rule 0 = min, 1 = max; W compute waves per workgroup.
-hipError_t launch_sweep(int dtype, int rule, int W, int nwg, const KArgs& args, hipStream_t stream);
+// dtype 0 = f32, 1 = i32; rule 0 = min, 1 = max; W compute waves per workgroup of R rows
+// per lane: (W, R) = (1, 1), (2, 1) or (1, 2).
+hipError_t launch_sweep(int dtype, int rule, int W, int R, int nwg, const KArgs& args, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t stream);
-// LDS bytes per workgroup for W compute waves (for occupancy decisions).
-size_t lds_bytes(int W);
+// LDS bytes per workgroup (for occupancy decisions).
+size_t lds_bytes(int W, int R);
 
 // The allocation-free entry point's fixed device workspace: NOALLOC_CTL_WORDS control
 // words (padded to 256 bytes), then handoff rows.  noalloc_scratch() returns its

@@ -45,30 +45,38 @@
 // device-wide abort flag and all waits end, so a kernel always drains.
 #include "wf_internal.h"
 
+#include <stddef.h>
+
 namespace wfk {
 namespace {
 
 constexpr int CHUNK = 16;               // positions per IO chunk
-constexpr int SLOT = 64 * CHUNK * 4;    // bytes of one chunk slot (64 rows x 16 positions)
+constexpr int SLAB = 64 * CHUNK * 4;    // bytes of one chunk of 64 lane rows (16 positions each)
 constexpr int C_SLOTS = 8;              // chunk slots of the c ring
 constexpr int H_SLOTS = 8;              // chunk slots of the H ring (slack for the storer's jitter)
 constexpr int RING_T = 512;             // positions held by the T ring
-// Inside a slot, the 16 bytes of row r, quad q (positions 4q..4q+3 of the chunk)
-// sit at (r/16)*1024 + (r%16)*64 + q*16: a 1024-byte block holds 16 whole rows of
-// the chunk.  A 64-lane LDS-DMA load (lane L -> byte 16L) then fills one block with
-// lanes 4j..4j+3 reading one row's 64 contiguous bytes, so the global accesses of
+// A chunk slot holds R slabs: slab s holds grid row R*r + s of every lane r (R rows
+// per lane).  Inside a slab, the 16 bytes of lane row r, quad q (positions 4q..4q+3 of
+// the chunk) sit at (r/16)*1024 + (r%16)*64 + 16*(q ^ swz(r)): a 1024-byte block holds
+// 16 whole rows of the chunk, each row's four quads in its own 64 contiguous bytes in
+// a per-row order.  A 64-lane LDS-DMA load (lane L -> byte 16L) then fills one block
+// with lanes 4j..4j+3 reading one row's 64 contiguous bytes, so the global accesses of
 // four consecutive lanes coalesce; the storer reads the H ring the same way.  The
-// compute wave's per-row 16-byte accesses to one quad are 64 bytes apart (a 4-way
-// bank conflict on these few prefetch reads and stores).
+// per-row quad order spreads the compute wave's accesses to one quad of its 64 rows
+// (64 bytes apart) over all banks: any 8 consecutive lanes hit 8 distinct 16-byte
+// bank groups (row parity picks the half of 128 bytes, swz(r) the quad within it).
 constexpr int QUAD = 16;
 __device__ __forceinline__ int lane_off(int r) { return (r >> 4) * 1024 + (r & 15) * 64; }
+__device__ __forceinline__ int swz(int r) { return (r >> 1) & 3; }
+// Byte offset of lane row r's logical quad q inside a slab.
+__device__ __forceinline__ int quad_off(int r, int q) { return lane_off(r) + QUAD * (q ^ swz(r)); }
 
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u4a4 __attribute__((ext_vector_type(4), aligned(4)));
 
+// Per compute wave: the T ring and the control words.  The c and H rings (which depend
+// on R) are in WaveRings.
 struct alignas(16) WaveLds {
-  unsigned char cring[C_SLOTS * SLOT];
-  unsigned char hring[H_SLOTS * SLOT];
   uint32_t tring[RING_T];
   uint32_t c_ready;   // chunks of c committed to cring (IO -> compute)
   uint32_t h_done;    // positions of H stored out of hring (IO -> compute)
@@ -83,6 +91,12 @@ struct alignas(16) WaveLds {
   uint64_t tr_t_wait;       // compute cycles waiting for T quads
   uint64_t tr_load_wait;    // loader cycles waiting for a free c slot
   uint64_t tr_pad;
+};
+
+template <int R>
+struct alignas(16) WaveRings {
+  unsigned char cring[C_SLOTS * R * SLAB];
+  unsigned char hring[H_SLOTS * R * SLAB];
 };
 
 #define CBAR() asm volatile("" ::: "memory")
@@ -141,9 +155,12 @@ template <typename T, int RULE> __device__ __forceinline__ u4 absent4() {
   return u4{v, v, v, v};
 }
 
-// End of the T positions a walk of G groups reads: its last chunk (number NC - 1, NC =
-// ceil(4G / 16)) checks positions up to 16 (NC - 1) + 64 + 16.
-__host__ __device__ constexpr int t_pad_end(int G) { return CHUNK * ((4 * G + CHUNK - 1) / CHUNK) + 64; }
+// End of the T positions a walk of G groups with R rows per lane reads: its last chunk
+// (number NC - 1, NC = ceil(4G / 16)) checks positions up to 16 (NC - 1) + 64 R + 16.
+__host__ __device__ constexpr int t_pad_end(int G, int R) { return CHUNK * ((4 * G + CHUNK - 1) / CHUNK) + 64 * R; }
+// First T position a walk reads: the quad of columns -3 .. 0 of the row above the band
+// (position p holds the row above at column p - (64 R - 1)).
+__host__ __device__ constexpr int t_first(int R) { return 64 * R - 4; }
 
 template <typename T> __device__ __forceinline__ T dpp_shr1(T old, T src) {
   return from_bits<T>((uint32_t)__builtin_amdgcn_update_dpp((int)bits(old), (int)bits(src), 0x138, 0xf, 0xf, false));
@@ -294,52 +311,68 @@ __device__ __noinline__ u4 wait_quad(const lds_u8* tp, WaveLds* lds, uint32_t* c
   return q;
 }
 
-// Reads of chunk kn's inputs for one lane: its four c quads and its four T quads (the
-// T ring is fed up to the padding past the band's last position, so every chunk has
-// four).  A read past the last chunk only picks up unused stale data.
-__device__ __forceinline__ void read_chunk(int kn, const lds_u8* crow, const lds_u8* tr_base, u4 (&c)[4],
-                                           u4 (&t)[4]) {
-  const lds_u8* cb = crow + (kn % C_SLOTS) * SLOT;
-  const int tpos = (CHUNK * kn + 64) & (RING_T - 1);
+// Reads of chunk kn's inputs for one lane: its 4 R c quads (cq[q]: this lane's logical
+// quad q in slab 0 of slot 0) and its four T quads (the T ring is fed up to the
+// padding past the band's last position, so every chunk has four).  A read past the
+// last chunk only picks up unused stale data.
+template <int R>
+__device__ __forceinline__ void read_chunk(int kn, const lds_u8* const (&cq)[4], const lds_u8* tr_base,
+                                           u4 (&c)[R][4], u4 (&t)[4]) {
+  const int sb = (kn % C_SLOTS) * (R * SLAB);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) c[q] = lds_ld4(cb + QUAD * q);
+  for (int s = 0; s < R; ++s)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c[s][q] = lds_ld4(cq[q] + sb + s * SLAB);
+  const int tpos = (CHUNK * kn + 64 * R) & (RING_T - 1);
 #pragma unroll
   for (int q = 0; q < 4; ++q) t[q] = lds_ld4(tr_base + (tpos + 4 * q) * 4);
 }
 
 // Control words a chunk start checks, read ahead of time.  The counters only grow, so
 // a check that passes on values read earlier also passes on current ones; one that
-// fails falls back to waiting on fresh reads.
+// fails falls back to waiting on fresh reads.  This wave's words are read with one
+// 16-byte LDS read and kept in vector registers until the check: taking scalar copies
+// right after the read would make the walk wait for it mid-chunk.
 struct CtlSnap {
-  uint32_t c_ready, h_done, cons_t_reset;
+  u4 own;                 // c_ready, h_done, progress, t_reset of this wave
+  uint32_t cons_t_reset;  // the consumer wave's t_reset (CONS == 1)
 };
+static_assert(offsetof(WaveLds, c_ready) % 16 == 0 && offsetof(WaveLds, h_done) == offsetof(WaveLds, c_ready) + 4,
+              "c_ready and h_done open an aligned quad");
 
 template <int CONS>
 __device__ __forceinline__ void snap_ctl(WaveLds& L, WaveLds* C, CtlSnap& s) {
-  s.c_ready = ld_ctl(&L.c_ready);
-  s.h_done = ld_ctl(&L.h_done);
+  s.own = lds_ld4_fresh(L8(&L.c_ready));
   s.cons_t_reset = CONS == 1 ? ld_ctl(&C->t_reset) : 0u;
 }
 
 // One chunk (4 groups of 4 steps) of the walk, computed from the inputs read during the
 // previous chunk (cc, tc) while the next chunk's inputs are read into (cn, tn).
+// Lane r owns the R rows R r .. R r + R - 1 of the strip (sub-rows s = 0 .. R-1); row
+// R r + s handles column t - (R r + s) at step t.  Sub-row 0's N comes from lane r-1's
+// last sub-row by DPP (lane 0: the T value), its NW is the previous step's N; sub-row
+// s > 0 takes N and NW from sub-row s-1 of the same lane (its values one and two steps
+// back).  The R cells of a step depend only on earlier steps, so they run side by side.
 // The T quads of the chunk are validated together at its start (the group loop then runs
 // without branches): when the producer is not that far yet, the chunk waits for the
 // chunk's last quad, which the producer writes after the others.
-// KIND 0: the first four chunks, where lanes left of column 0 keep their boundary value;
+// KIND 0: the first 4 R chunks, where rows left of column 0 keep their boundary value;
 // KIND 1: every later chunk.  The T ring is fed past the band's last T position with
 // absent values, so KIND 1 chunks read and check all four quads; groups past the last
 // one (g >= G) compute cells right of the grid, which nothing stores or reads.
 // CONS: 0 = no consumer, 1 = the next compute wave (LDS), 2 = the next band (global
 // handoff row).
-template <typename T, int RULE, int KIND, int CONS>
+template <typename T, int RULE, int R, int KIND, int CONS>
 __device__ __forceinline__ void compute_chunk(
     int k, int G, int gT, int NCc, WaveLds* lds, WaveLds& L, WaveLds* C,
-    __amdgpu_buffer_rsrc_t hand_out, const lds_u8* crow, lds_u8* hrow, lds_u8* ct_base, bool lane63, int lane,
-    const u4 (&cc)[4], u4 (&tc)[4], u4 (&cn)[4], u4 (&tn)[4], uint32_t& tprev_w, T& H, T& Np,
-    CtlSnap& snap, const KArgs& a, uint64_t* crec) {
+    __amdgpu_buffer_rsrc_t hand_out, const lds_u8* const (&cq)[4], lds_u8* const (&hq)[4], lds_u8* ct_base,
+    bool lane63, int lane, const u4 (&cc)[R][4], u4 (&tc)[4], u4 (&cn)[R][4], u4 (&tn)[4], uint32_t& tprev_w,
+    T (&H)[R], T (&Hp)[R], T& Np, CtlSnap& snap, const KArgs& a, uint64_t* crec) {
   const uint32_t SENT = Num<T>::SENT;
   const int pos = CHUNK * k;
+  // Keep the chunk-start check (and the scalar copies of the control snapshot it takes)
+  // from being scheduled into the previous chunk's walk.
+  __builtin_amdgcn_sched_barrier(0);
   // Per-chunk records are sampled (every CTRACE_EVERY-th chunk): each clock read is a
   // scalar-memory round trip that would otherwise slow the walk being measured.
   __attribute__((address_space(1))) uint64_t* rec =
@@ -357,12 +390,14 @@ __device__ __forceinline__ void compute_chunk(
     const int need_h = pos + CHUNK - H_SLOTS * CHUNK;
     const int need_t = pos + CHUNK - RING_T;
     auto ok = [&](const CtlSnap& v) {
-      return (int)v.c_ready >= need_c && (int)v.h_done >= need_h && (CONS != 1 || (int)v.cons_t_reset >= need_t);
+      return (int)__builtin_amdgcn_readfirstlane(v.own.x) >= need_c &&
+             (int)__builtin_amdgcn_readfirstlane(v.own.y) >= need_h &&
+             (CONS != 1 || (int)v.cons_t_reset >= need_t);
     };
     if (!ok(snap)) {
       const uint64_t c0 = a.trace ? __builtin_readcyclecounter() : 0;
       if (rec && lane == 0) {
-        rec[3] = ((int)snap.c_ready < need_c ? 1u : 0u) | ((int)snap.h_done < need_h ? 2u : 0u) |
+        rec[3] = ((int)snap.own.x < need_c ? 1u : 0u) | ((int)snap.own.y < need_h ? 2u : 0u) |
                  (CONS == 1 && (int)snap.cons_t_reset < need_t ? 8u : 0u);
       }
       wait_until<false>([&] { snap_ctl<CONS>(L, C, snap); return ok(snap); }, lds, a);
@@ -375,8 +410,8 @@ __device__ __forceinline__ void compute_chunk(
   }
   CBAR();
   const lds_u8* tr_base = L8(L.tring);
-  const int tpos = (pos + 64) & (RING_T - 1);  // T ring position of group 4k's quad
-  // Validate the chunk's T quads (all four; in the first four chunks, those of groups
+  const int tpos = (pos + 64 * R) & (RING_T - 1);  // T ring position of group 4k's quad
+  // Validate the chunk's T quads (all four; in the first 4 R chunks, those of groups
   // below gT, whose quads hold columns of the grid).  All four words of a quad
   // are checked: a 16-byte LDS read racing a 16-byte write from another wave may see
   // part of it.  All lanes read the same quads, so the test is wave-uniform.
@@ -415,10 +450,10 @@ __device__ __forceinline__ void compute_chunk(
       lds_st4(L8(L.tring) + (tpos + 4 * lane) * 4, s4);
     }
     CBAR();
-    if (lane == 0) st_ctl(&L.t_reset, (uint32_t)(pos + 64 + 4 * nq));
+    if (lane == 0) st_ctl(&L.t_reset, (uint32_t)(pos + 64 * R + 4 * nq));
   }
-  read_chunk(k + 1, crow, tr_base, cn, tn);
-  lds_u8* hb = hrow + (k % H_SLOTS) * SLOT;
+  read_chunk<R>(k + 1, cq, tr_base, cn, tn);
+  const int hb = (k % H_SLOTS) * (R * SLAB);
   lds_u8* ct = ct_base + (pos & (RING_T - 1)) * 4;
   // Bottom-row quads of the chunk for the next band, gathered into lanes 60..63 (lane 63
   // holds the last group's quad, lane 62 the one before, ...) and stored once at the end
@@ -429,72 +464,94 @@ __device__ __forceinline__ void compute_chunk(
     const int g = 4 * k + q;
     // The next chunk start's checks, read while this last group runs.
     if (q == 3) snap_ctl<CONS>(L, C, snap);
-    const u4 cv = cc[q];
     const u4 tv = tc[q];
     const uint32_t tk[4] = {tprev_w, tv.x, tv.y, tv.z};
     if (KIND == 1 || g < gT) tprev_w = tv.w;
-    u4 h4;
+    u4 h4[R];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const T N = dpp_shr1<T>(from_bits<T>(tk[e]), H);
-      T Hn = Num<T>::add(from_bits<T>(cv[e]), Num<T>::template op3<RULE>(N, Np, H));
-      if (KIND == 0) Hn = (4 * g + e < lane) ? H : Hn;  // lanes left of column 0 keep the left boundary
+      const T N = dpp_shr1<T>(from_bits<T>(tk[e]), H[R - 1]);
+      T Hn[R];
+      // The lower sub-rows first: they read only registers of this lane, which leaves the
+      // DPP source (the last sub-row) written a few instructions before the next step's move.
+#pragma unroll
+      for (int sr = R - 1; sr >= 1; --sr)
+        Hn[sr] = Num<T>::add(from_bits<T>(cc[sr][q][e]), Num<T>::template op3<RULE>(H[sr - 1], Hp[sr - 1], H[sr]));
+      Hn[0] = Num<T>::add(from_bits<T>(cc[0][q][e]), Num<T>::template op3<RULE>(N, Np, H[0]));
+      if (KIND == 0) {
+        // rows left of column 0 keep the left boundary
+#pragma unroll
+        for (int sr = 0; sr < R; ++sr) Hn[sr] = (4 * g + e < R * lane + sr) ? H[sr] : Hn[sr];
+      }
       Np = N;
-      H = Hn;
-      h4[e] = bits(H);
+#pragma unroll
+      for (int sr = 0; sr < R; ++sr) {
+        Hp[sr] = H[sr];
+        H[sr] = Hn[sr];
+        h4[sr][e] = bits(H[sr]);
+      }
     }
-    // H into the ring, bottom row to the consumer.  Positions < 60 are never read by a consumer.
-    lds_st4(hb + QUAD * q, h4);
-    if (CONS == 1 && (KIND != 0 || g >= 15)) {
+    // H into the ring, bottom row to the consumer.  Positions below t_first(R) are never
+    // read by a consumer.
+#pragma unroll
+    for (int sr = 0; sr < R; ++sr) lds_st4(hq[q] + hb + sr * SLAB, h4[sr]);
+    if (CONS == 1 && (KIND != 0 || g >= 16 * R - 1)) {
       // Past the last group the consumer's ring gets absent values (its padding).
-      if (lane63) lds_st4(ct + 16 * q, g < G ? h4 : absent4<T, RULE>());
+      if (lane63) lds_st4(ct + 16 * q, g < G ? h4[R - 1] : absent4<T, RULE>());
     }
     if (CONS == 2) {
-      if (q == 0) hand4 = h4;  // lane 63 holds group 0's quad; the other lanes' values are shifted out
-      else shift_in_lane63(hand4, h4);
+      if (q == 0) hand4 = h4[R - 1];  // lane 63 holds group 0's quad; the other lanes' values are shifted out
+      else shift_in_lane63(hand4, h4[R - 1]);
     }
   }
   if (CONS == 2) {
-    // Lane 60+q holds group 4k+q's quad.  Only positions [60, 4G) are written: the
-    // others are never read by a consumer and stay at the sentinel.
+    // Lane 60+q holds group 4k+q's quad.  Only positions [t_first(R), 4G) are written:
+    // the others are never read by a consumer and stay at the sentinel.
     const int g = 4 * k + lane - 60;
-    if (lane >= 60 && g < G && (KIND != 0 || g >= 15))
+    if (lane >= 60 && g < G && (KIND != 0 || g >= 16 * R - 1))
       __builtin_amdgcn_raw_buffer_store_b128(hand4, hand_out, 16 * g, 0, CPOL_SC1);
   }
 }
 
-template <typename T, int RULE, int CONS>
-__device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLds& L, WaveLds* C, __amdgpu_buffer_rsrc_t hand_out,
-                             lds_u8* crow, lds_u8* hrow, int lane, T H, const KArgs& a, uint64_t* crec) {
+template <typename T, int RULE, int R, int CONS>
+__device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLds& L, WaveLds* C,
+                                             __amdgpu_buffer_rsrc_t hand_out, const lds_u8* const (&cq)[4],
+                                             lds_u8* const (&hq)[4], int lane, const T (&Hinit)[R], const KArgs& a,
+                                             uint64_t* crec) {
   const int NCc = (4 * G + CHUNK - 1) / CHUNK;
   lds_u8* ct_base = CONS == 1 ? L8(C->tring) : nullptr;
   const bool lane63 = lane == 63;
-  // First T quad: positions 60..63 = columns -3..0 of the row above (.z is the corner, .w column 0).
-  u4 tprev = lds_ld4_fresh(L8(L.tring) + 60 * 4);
+  constexpr int TF = t_first(R);
+  // First T quad: columns -3..0 of the row above (.z is the corner, .w column 0).
+  u4 tprev = lds_ld4_fresh(L8(L.tring) + TF * 4);
   if (Num<T>::probe(tprev) == Num<T>::SENT)
-    tprev = wait_quad<T>(L8(L.tring) + 60 * 4, lds, a.ctl, a.watchdog_ticks, nullptr);
+    tprev = wait_quad<T>(L8(L.tring) + TF * 4, lds, a.ctl, a.watchdog_ticks, nullptr);
   if (a.trace && lane == 0) L.tr_first = __builtin_readcyclecounter();
   T Np = from_bits<T>(tprev.z);
   uint32_t tprev_w = tprev.w;
   if (lane == 0) {
     const u4 s4 = {Num<T>::SENT, Num<T>::SENT, Num<T>::SENT, Num<T>::SENT};
-    lds_st4(L8(L.tring) + 60 * 4, s4);
+    lds_st4(L8(L.tring) + TF * 4, s4);
   }
+  T H[R], Hp[R];
+#pragma unroll
+  for (int sr = 0; sr < R; ++sr) H[sr] = Hp[sr] = Hinit[sr];
   // Inputs of the current chunk and of the next one, in two register sets used in turn.
-  u4 cA[4], tA[4], cB[4], tB[4];
+  u4 cA[R][4], tA[4], cB[R][4], tB[4];
   wait_until<false>([&] { return ld_ctl(&L.c_ready) >= 1u; }, lds, a);
   CBAR();
-  read_chunk(0, crow, L8(L.tring), cA, tA);
+  read_chunk<R>(0, cq, L8(L.tring), cA, tA);
 #pragma unroll
   for (int q = 0; q < 4; ++q) tB[q] = tA[q];
   CtlSnap snap;
   snap_ctl<CONS>(L, C, snap);
-#define WF_CHUNK(KIND, KK, CUR_C, CUR_T, NXT_C, NXT_T)                                                        \
-  compute_chunk<T, RULE, KIND, CONS>(KK, G, gT, NCc, lds, L, C, hand_out, crow, hrow, ct_base, lane63, lane,  \
-                                     CUR_C, CUR_T, NXT_C, NXT_T, tprev_w, H, Np, snap, a, crec)
+#define WF_CHUNK(KIND, KK, CUR_C, CUR_T, NXT_C, NXT_T)                                                         \
+  compute_chunk<T, RULE, R, KIND, CONS>(KK, G, gT, NCc, lds, L, C, hand_out, cq, hq, ct_base, lane63, lane,    \
+                                        CUR_C, CUR_T, NXT_C, NXT_T, tprev_w, H, Hp, Np, snap, a, crec)
   int k = 0;
-  // The first four chunks (groups 0..15, where lanes left of column 0 are masked).
-  for (; k < 4; k += 2) {
+  // The first 4 R chunks (groups 0 .. 16 R - 1, where rows left of column 0 are masked;
+  // a walk always has at least that many).
+  for (; k < 4 * R; k += 2) {
     WF_CHUNK(0, k, cA, tA, cB, tB);
     WF_CHUNK(0, k + 1, cB, tB, cA, tA);
   }
@@ -506,7 +563,7 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   }
   if (k < NCc) WF_CHUNK(1, k, cA, tA, cB, tB);
 #undef WF_CHUNK
-  const int t_pad = t_pad_end(G);
+  const int t_pad = t_pad_end(G, R);
   if (CONS == 1) {
     // The consumer's last chunks read T positions [16 NCc, t_pad), past every group of
     // this walk: fill them with absent values once its ring has room.
@@ -523,37 +580,46 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   }
 }
 
-template <typename T, int RULE, int W>
-__device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLds* lds, int w, int lane, const KArgs& a,
-                                             uint64_t* crec) {
+template <typename T, int RULE, int W, int R>
+__device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLds* lds, WaveRings<R>* rings, int w,
+                                             int lane, const KArgs& a, uint64_t* crec) {
   WaveLds& L = lds[w];
   const int64_t m = g.m, n = g.n;
-  const int64_t row0 = (int64_t)band * (64 * W) + 64 * w;
+  const int64_t row0 = (int64_t)band * (64 * R * W) + 64 * R * w;
   if (row0 >= m) return;
   // The walk is the critical path: let it win the compute unit's shared units (LDS,
   // scalar and instruction issue) over the staging waves.
   __builtin_amdgcn_s_setprio(3);
-  const int G = (int)groups_for(n);
+  const int G = (int)groups_for(n, R);
   const int gT = n >= 2 ? (int)((n - 2) / 4 + 1) : 0;
-  const bool lds_consumer = (w + 1 < W && row0 + 64 < m);
+  const bool lds_consumer = (w + 1 < W && row0 + 64 * R < m);
   // (The fault hook drops one band's handoff: its consumer then waits until the watchdog fires.)
   const bool glob_consumer = (w == W - 1) && (band + 1 < g.nbands) && a.fault_band != (uint32_t)band + 1u;
-  const int64_t row = row0 + lane;
   if (a.trace && lane == 0) {
     L.tr_start = __builtin_readcyclecounter();
     L.tr_wall = wall_clock64();
   }
-  T H = Num<T>::template absent<RULE>();
-  if (g.left && row < m) H = GC<T>(g.left)[row];
-  lds_u8* crow = L8(L.cring) + lane_off(lane);
-  lds_u8* hrow = L8(L.hring) + lane_off(lane);
+  T H[R];
+#pragma unroll
+  for (int sr = 0; sr < R; ++sr) {
+    const int64_t row = row0 + R * lane + sr;
+    H[sr] = Num<T>::template absent<RULE>();
+    if (g.left && row < m) H[sr] = GC<T>(g.left)[row];
+  }
+  const lds_u8* cq[4];
+  lds_u8* hq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    cq[q] = L8(rings[w].cring) + quad_off(lane, q);
+    hq[q] = L8(rings[w].hring) + quad_off(lane, q);
+  }
   if (lds_consumer) {
-    compute_walk<T, RULE, 1>(G, gT, lds, L, &lds[w + 1], __amdgpu_buffer_rsrc_t(), crow, hrow, lane, H, a, crec);
+    compute_walk<T, RULE, R, 1>(G, gT, lds, L, &lds[w + 1], __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec);
   } else if (glob_consumer) {
     __amdgpu_buffer_rsrc_t hand_out = make_rsrc(g.hand + (int64_t)band * g.hand_ld, (uint32_t)(g.hand_ld * 4));
-    compute_walk<T, RULE, 2>(G, gT, lds, L, nullptr, hand_out, crow, hrow, lane, H, a, crec);
+    compute_walk<T, RULE, R, 2>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec);
   } else {
-    compute_walk<T, RULE, 0>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), crow, hrow, lane, H, a, crec);
+    compute_walk<T, RULE, R, 0>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec);
   }
   if (a.trace && lane == 0) L.tr_end = __builtin_readcyclecounter();
 }
@@ -577,24 +643,25 @@ struct BandGeom {
   int G, NC, T_END;
 };
 
-template <int W>
+template <int W, int R>
 __device__ __forceinline__ BandGeom band_geom(const GridDesc& g, int band, int w) {
   BandGeom b;
   b.m = g.m;
   b.n = g.n;
-  b.row0 = (int64_t)band * (64 * W) + 64 * w;
-  b.G = (int)groups_for(g.n);
+  b.row0 = (int64_t)band * (64 * R * W) + 64 * R * w;
+  b.G = (int)groups_for(g.n, R);
   b.NC = (4 * b.G + CHUNK - 1) / CHUNK;
   b.T_END = 4 * b.G;
   return b;
 }
 
 // ------------------------------------------------------------- loader
-// Chunk k of c for the 64 rows of a strip goes straight from memory into c-ring
-// slot k % C_SLOTS with LDS-DMA loads (buffer_load_dwordx4 ... lds): load i
-// covers rows 16i .. 16i+15, lane L reading row 16i + L/4 at positions
-// 16k + 4(L%4) .. +3, i.e. columns col .. col+3 with col = 16k + 4(L%4) - row.
-// The hardware writes lane L's 16 bytes at M0 + 16L, which is the slot layout.
+// Chunk k of c for the 64 R rows of a strip goes straight from memory into c-ring
+// slot k % C_SLOTS with LDS-DMA loads (buffer_load_dwordx4 ... lds): load (s, i)
+// covers lane rows 16i .. 16i+15 of slab s, lane L reading grid row
+// rho = R (16i + L/4) + s at positions 16k + 4q .. +3, q = (L%4) ^ swz(16i + L/4),
+// i.e. columns col .. col+3 with col = 16k + 4q - rho.  The hardware writes lane L's
+// 16 bytes at M0 + 16L, which is the slab layout.
 //
 // Offsets are taken from a buffer descriptor based at the strip's first row
 // and ending at the grid's last element: quads left of a row's column 0 pick
@@ -616,25 +683,35 @@ __device__ __forceinline__ void dma_quad16(__amdgpu_buffer_rsrc_t rsrc, uint32_t
 }
 #pragma clang diagnostic pop
 
-// Wait until at most 4*younger DMA loads of this wave are outstanding.
+// Wait until at most `younger` chunks of 4 R DMA loads each are outstanding.
+template <int R>
 __device__ __forceinline__ void wait_dma(int younger) {
-  switch (younger) {
+  switch (4 * R * younger) {
     case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
-    case 1: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
-    case 2: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
-    case 3: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
-    case 4: asm volatile("s_waitcnt vmcnt(16)" ::: "memory"); break;
-    case 5: asm volatile("s_waitcnt vmcnt(20)" ::: "memory"); break;
-    case 6: asm volatile("s_waitcnt vmcnt(24)" ::: "memory"); break;
-    default: asm volatile("s_waitcnt vmcnt(28)" ::: "memory"); break;
+    case 4: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+    case 8: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
+    case 12: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
+    case 16: asm volatile("s_waitcnt vmcnt(16)" ::: "memory"); break;
+    case 20: asm volatile("s_waitcnt vmcnt(20)" ::: "memory"); break;
+    case 24: asm volatile("s_waitcnt vmcnt(24)" ::: "memory"); break;
+    case 28: asm volatile("s_waitcnt vmcnt(28)" ::: "memory"); break;
+    case 32: asm volatile("s_waitcnt vmcnt(32)" ::: "memory"); break;
+    case 36: asm volatile("s_waitcnt vmcnt(36)" ::: "memory"); break;
+    case 40: asm volatile("s_waitcnt vmcnt(40)" ::: "memory"); break;
+    case 44: asm volatile("s_waitcnt vmcnt(44)" ::: "memory"); break;
+    case 48: asm volatile("s_waitcnt vmcnt(48)" ::: "memory"); break;
+    case 52: asm volatile("s_waitcnt vmcnt(52)" ::: "memory"); break;
+    case 56: asm volatile("s_waitcnt vmcnt(56)" ::: "memory"); break;
+    default: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
   }
 }
-static_assert(C_SLOTS <= 8, "wait_dma covers at most 7 younger chunks");
+static_assert(C_SLOTS <= 8, "wait_dma covers at most 7 younger chunks of 8 loads");
 
+template <int R>
 struct LoaderLanes {
-  int64_t rel[4];    // element offset of (row, column 16k' + 4(L%4) - row) for k' = 0, from the strip base
-  int rho[4];        // row inside the strip (not clamped)
-  bool real[4];      // the row exists
+  int64_t rel[R][4];  // element offset of (row, column 16k' + 4q - row) for k' = 0, from the strip base
+  int rho[R][4];      // row inside the strip (not clamped)
+  bool real[R][4];    // the row exists
 };
 
 // Idle step of a polling IO wave: sleep, then check abort and the watchdog.
@@ -655,34 +732,42 @@ __device__ __forceinline__ bool io_idle(WaveLds* lds, const KArgs& a, Watch& w, 
   return true;
 }
 
-template <int W>
-__device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds* lds, int w, int lane,
-                                            const KArgs& a, uint32_t item) {
-  const BandGeom B = band_geom<W>(g, band, w);
+// Logical quad a loader or storer lane moves: lane L covers physical quad L%4 of lane
+// row 16i + L/4, whose swizzle is ((L/4) >> 1) & 3 whatever i.
+__device__ __forceinline__ int io_quad(int lane) { return (lane & 3) ^ ((lane >> 3) & 3); }
+
+template <int W, int R>
+__device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds* lds, WaveRings<R>* rings, int w,
+                                            int lane, const KArgs& a, uint32_t item) {
+  const BandGeom B = band_geom<W, R>(g, band, w);
   if (B.row0 >= B.m) return;
   WaveLds& L = lds[w];
+  unsigned char* cring = rings[w].cring;
   // Elements from the strip's first row to the end of the grid.
   const int64_t span = (B.m - 1 - B.row0) * g.ld_cost + B.n;
   const uint32_t span_bytes = (uint32_t)(span * 4 < 0xFFFFFFF0ll ? span * 4 : 0xFFFFFFF0ll);
   const __amdgpu_buffer_rsrc_t rsrc = make_rsrc((const uint32_t*)g.cost + B.row0 * g.ld_cost, span_bytes);
   const int64_t last_rho = B.m - 1 - B.row0;
-  LoaderLanes ln;
+  const int lq = io_quad(lane);
+  LoaderLanes<R> ln;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int rho = 16 * i + (lane >> 2);
-    const int64_t rr = rho < last_rho ? rho : last_rho;
-    ln.rho[i] = rho;
-    ln.real[i] = rho <= last_rho;
-    ln.rel[i] = rr * g.ld_cost + 4 * (lane & 3) - rho;
-  }
-  const uint32_t slot0 = (uint32_t)(uintptr_t)L8(L.cring);
+  for (int s = 0; s < R; ++s)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rho = R * (16 * i + (lane >> 2)) + s;
+      const int64_t rr = rho < last_rho ? rho : last_rho;
+      ln.rho[s][i] = rho;
+      ln.real[s][i] = rho <= last_rho;
+      ln.rel[s][i] = rr * g.ld_cost + 4 * lq - rho;
+    }
+  const uint32_t slot0 = (uint32_t)(uintptr_t)L8(cring);
   const int NC = B.NC;
   // Chunks [0, k_clean) of a full strip have every lane's quads inside the grid: they
   // are issued from precomputed byte offsets (chunk k adds 64k) with no per-lane checks
-  // and need no fix-up.  The largest offset of chunk k is that of row 63, quad 3.
+  // and need no fix-up.  The largest offset of chunk k is that of row 64 R - 1, quad 3.
   int k_clean = 0;
-  if (B.row0 + 63 <= B.m - 1) {
-    const int64_t max_rel = 63 * g.ld_cost + 12 - 63;
+  if (B.row0 + 64 * R - 1 <= B.m - 1) {
+    const int64_t max_rel = (int64_t)(64 * R - 1) * g.ld_cost + 12 - (64 * R - 1);
     const int64_t room = span - 4 - max_rel;
     if (room >= 0) k_clean = (int)(room / 16 + 1 < NC ? room / 16 + 1 : NC);
   }
@@ -695,9 +780,11 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
     const int k_pad = B.n >= 16 ? (int)((B.n - 16) / 16 + 1) : 0;  // first k with 16k + 15 >= n
     if (k_clean > k_pad) k_clean = k_pad;
   }
-  uint32_t voff0[4];
+  uint32_t voff0[R][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) voff0[i] = (uint32_t)(ln.rel[i] * 4);  // used only for clean chunks
+  for (int s = 0; s < R; ++s)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) voff0[s][i] = (uint32_t)(ln.rel[s][i] * 4);  // used only for clean chunks
   int issued = 0, committed = 0;
   Watch t_idle;
   uint32_t polls = 0;
@@ -705,27 +792,32 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
     // Issue every chunk whose slot the compute wave has released: slot k % C_SLOTS
     // last held chunk k - C_SLOTS, read completely once progress >= 16 (k - C_SLOTS + 1).
     while (issued < NC && (int)ld_ctl(&L.progress) >= 16 * (issued - C_SLOTS + 1)) {
-      const uint32_t base = __builtin_amdgcn_readfirstlane(slot0 + (uint32_t)((issued % C_SLOTS) * SLOT));
+      const uint32_t base = __builtin_amdgcn_readfirstlane(slot0 + (uint32_t)((issued % C_SLOTS) * (R * SLAB)));
       if (glb_u64* r = chunk_rec(a, item, W, w, issued))
         if (lane == 0) r[4] = wall_clock64();
       if (issued < k_clean) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) dma_quad16(rsrc, voff0[i] + 64u * (uint32_t)issued, base + 1024u * i);
+        for (int s = 0; s < R; ++s)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            dma_quad16(rsrc, voff0[s][i] + 64u * (uint32_t)issued, base + (uint32_t)(SLAB * s + 1024 * i));
       } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int64_t e = ln.rel[i] + 16 * issued;  // element offset from the strip base
-          // Quads not wholly inside [strip base, end of grid) are not loaded at all (an
-          // out-of-range offset): rows past the end of a ragged strip and the grid's tail.
-          const uint32_t voff = (e < 0 || e + 4 > span) ? 0xFFFFFFFFu : (uint32_t)(e * 4);
-          dma_quad16(rsrc, voff, base + 1024u * i);
-        }
+        for (int s = 0; s < R; ++s)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int64_t e = ln.rel[s][i] + 16 * issued;  // element offset from the strip base
+            // Quads not wholly inside [strip base, end of grid) are not loaded at all (an
+            // out-of-range offset): rows past the end of a ragged strip and the grid's tail.
+            const uint32_t voff = (e < 0 || e + 4 > span) ? 0xFFFFFFFFu : (uint32_t)(e * 4);
+            dma_quad16(rsrc, voff, base + (uint32_t)(SLAB * s + 1024 * i));
+          }
       }
       ++issued;
     }
     if (committed < issued) {
       const int k = committed;
-      wait_dma(issued - committed - 1);
+      wait_dma<R>(issued - committed - 1);
       if (glb_u64* r = chunk_rec(a, item, W, w, k))
         if (lane == 0) r[5] = wall_clock64();
       if (k < k_clean) {
@@ -736,29 +828,33 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
         continue;
       }
       // Quads that straddle the end of the grid and hold columns of a real row.
-      bool fix[4];
+      bool fix[R][4];
       bool any = false;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t col = 16 * k + 4 * (lane & 3) - ln.rho[i];
-        const int64_t e = ln.rel[i] + 16 * k;
-        fix[i] = ln.real[i] && col + 3 >= 0 &&
-                 ((e + 4 > span && col <= B.n - 1) || (padded && col + 3 > B.n - 1));
-        any |= fix[i];
-      }
+      for (int s = 0; s < R; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t col = 16 * k + 4 * lq - ln.rho[s][i];
+          const int64_t e = ln.rel[s][i] + 16 * k;
+          fix[s][i] = ln.real[s][i] && col + 3 >= 0 &&
+                      ((e + 4 > span && col <= B.n - 1) || (padded && col + 3 > B.n - 1));
+          any |= fix[s][i];
+        }
       if (__builtin_amdgcn_ballot_w64(any)) {
         typedef __attribute__((address_space(1))) const uint32_t g32;
         const g32* cbase = (const g32*)(const void*)((const uint32_t*)g.cost + B.row0 * g.ld_cost);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          if (!fix[i]) continue;
-          const int64_t col = 16 * k + 4 * (lane & 3) - ln.rho[i];
-          u4 v;
+        for (int s = 0; s < R; ++s)
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            v[e] = (col + e >= 0 && col + e <= B.n - 1) ? cbase[(int64_t)ln.rho[i] * g.ld_cost + col + e] : 0u;
-          lds_st4(L8(L.cring) + (k % C_SLOTS) * SLOT + 1024 * i + 16 * lane, v);
-        }
+          for (int i = 0; i < 4; ++i) {
+            if (!fix[s][i]) continue;
+            const int64_t col = 16 * k + 4 * lq - ln.rho[s][i];
+            u4 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              v[e] = (col + e >= 0 && col + e <= B.n - 1) ? cbase[(int64_t)ln.rho[s][i] * g.ld_cost + col + e] : 0u;
+            lds_st4(L8(cring) + (k % C_SLOTS) * (R * SLAB) + SLAB * s + 1024 * i + 16 * lane, v);
+          }
         __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
       }
       CBAR();
@@ -776,137 +872,149 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
     if (a.trace && lane == 0) L.tr_load_wait += __builtin_readcyclecounter() - c0;
     if (!ok) break;
   }
-  wait_dma(0);  // nothing may still be writing the ring when the band ends
+  wait_dma<R>(0);  // nothing may still be writing the ring when the band ends
 }
 
-// Store chunk k of H (64 rows x 16 positions) from the H ring: lane L covers
-// row 16i + L/4, positions 16k + 4(L%4) .. +3 (contiguous LDS reads, and four
-// consecutive lanes store one row's 64 contiguous bytes).
+// Store chunk k of H (64 R rows x 16 positions) from the H ring: in slab s, lane L
+// covers lane row r = 16i + L/4 (grid row rho = R r + s), logical quad q = io_quad(L),
+// positions 16k + 4q .. +3 (contiguous LDS reads, and four consecutive lanes store one
+// row's 64 contiguous bytes).
 // Interior chunks (every quad inside the columns, none holding column n-1) take the
-// fast path: full strips store their four quads unconditionally (`qbase[i]` points at
-// the lane's quad of chunk 0, column 4(L%4) - row); the strip holding the last row
+// fast path: full strips store their quads unconditionally (`qbase[s][i]` points at
+// the lane's quad of chunk 0, column 4q - rho); the strip holding the last row
 // skips the rows past it and copies that row's quads to last_row as well.
+template <int R>
 __device__ __forceinline__ bool store_interior(const BandGeom& B, int k) {
-  return k >= 4 && 16 * (int64_t)k + 16 < B.n;
+  return k >= 4 * R && 16 * (int64_t)k + 16 < B.n;
 }
 
-template <bool LAST_STRIP>
-__device__ __forceinline__ void store_chunk_fast(const GridDesc& g, const BandGeom& B, WaveLds& L, int k, int lane,
-                                                 glb_u32* const (&qbase)[4]) {
-  u4 v[4];
+template <int R, bool LAST_STRIP>
+__device__ __forceinline__ void store_chunk_fast(const GridDesc& g, const BandGeom& B, const unsigned char* hring,
+                                                 int k, int lane, glb_u32* const (&qbase)[R][4]) {
+  u4 v[R][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) v[i] = lds_ld4(L8(L.hring) + (k % H_SLOTS) * SLOT + 1024 * i + 16 * lane);
+  for (int s = 0; s < R; ++s)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      v[s][i] = lds_ld4(L8(hring) + (k % H_SLOTS) * (R * SLAB) + SLAB * s + 1024 * i + 16 * lane);
   const bool full = g.mode == 0;
+  const int lq = io_quad(lane);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    if (!LAST_STRIP) {
-      if (full) *(glb_u4a4*)(qbase[i] + 16 * k) = v[i];
-    } else {
-      const int rho = 16 * i + (lane >> 2);
-      const int64_t row = B.row0 + rho;
-      if (row < B.m && full) *(glb_u4a4*)(qbase[i] + 16 * k) = v[i];
-      if (row == B.m - 1 && g.last_row)
-        *(glb_u4a4*)(G32((uint32_t*)g.last_row) + 16 * (int64_t)k + 4 * (lane & 3) - rho) = v[i];
-    }
-  }
-}
-
-__device__ __forceinline__ void store_chunk(const GridDesc& g, const BandGeom& B, WaveLds& L, int k, int lane) {
-  u4 v[4];
+  for (int s = 0; s < R; ++s)
 #pragma unroll
-  for (int i = 0; i < 4; ++i) v[i] = lds_ld4(L8(L.hring) + (k % H_SLOTS) * SLOT + 1024 * i + 16 * lane);
-  const bool full = g.mode == 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int rho = 16 * i + (lane >> 2);
-    const int64_t row = B.row0 + rho;
-    const int64_t col = 16 * k + 4 * (lane & 3) - rho;
-    if (row >= B.m || col > B.n - 1 || col + 3 < 0) continue;
-    if (full) {
-      glb_u32* op = G32((uint32_t*)g.out + row * g.ld_out);
-      if (col >= 0 && col + 3 <= B.n - 1) {
-        *(glb_u4a4*)(op + col) = v[i];
+    for (int i = 0; i < 4; ++i) {
+      if (!LAST_STRIP) {
+        if (full) *(glb_u4a4*)(qbase[s][i] + 16 * k) = v[s][i];
       } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (col + e >= 0 && col + e <= B.n - 1) op[col + e] = pick(v[i], e);
+        const int rho = R * (16 * i + (lane >> 2)) + s;
+        const int64_t row = B.row0 + rho;
+        if (row < B.m && full) *(glb_u4a4*)(qbase[s][i] + 16 * k) = v[s][i];
+        if (row == B.m - 1 && g.last_row)
+          *(glb_u4a4*)(G32((uint32_t*)g.last_row) + 16 * (int64_t)k + 4 * lq - rho) = v[s][i];
       }
     }
-    const bool has_last = col <= B.n - 1 && col + 3 >= B.n - 1;
-    if (has_last && g.last_col) G32((uint32_t*)g.last_col)[row] = pick(v[i], (int)(B.n - 1 - col));
-    if (row == B.m - 1) {
-      if (g.last_row) {
+}
+
+template <int R>
+__device__ __forceinline__ void store_chunk(const GridDesc& g, const BandGeom& B, const unsigned char* hring, int k,
+                                            int lane) {
+  u4 v[R][4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (col + e >= 0 && col + e <= B.n - 1) G32((uint32_t*)g.last_row)[col + e] = pick(v[i], e);
+  for (int s = 0; s < R; ++s)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      v[s][i] = lds_ld4(L8(hring) + (k % H_SLOTS) * (R * SLAB) + SLAB * s + 1024 * i + 16 * lane);
+  const bool full = g.mode == 0;
+  const int lq = io_quad(lane);
+#pragma unroll
+  for (int s = 0; s < R; ++s)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rho = R * (16 * i + (lane >> 2)) + s;
+      const int64_t row = B.row0 + rho;
+      const int64_t col = 16 * k + 4 * lq - rho;
+      if (row >= B.m || col > B.n - 1 || col + 3 < 0) continue;
+      const u4 x = v[s][i];
+      if (full) {
+        glb_u32* op = G32((uint32_t*)g.out + row * g.ld_out);
+        if (col >= 0 && col + 3 <= B.n - 1) {
+          *(glb_u4a4*)(op + col) = x;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (col + e >= 0 && col + e <= B.n - 1) op[col + e] = pick(x, e);
+        }
       }
-      if (has_last && g.final_cell) *G32((uint32_t*)g.final_cell) = pick(v[i], (int)(B.n - 1 - col));
+      const bool has_last = col <= B.n - 1 && col + 3 >= B.n - 1;
+      if (has_last && g.last_col) G32((uint32_t*)g.last_col)[row] = pick(x, (int)(B.n - 1 - col));
+      if (row == B.m - 1) {
+        if (g.last_row) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (col + e >= 0 && col + e <= B.n - 1) G32((uint32_t*)g.last_row)[col + e] = pick(x, e);
+        }
+        if (has_last && g.final_cell) *G32((uint32_t*)g.final_cell) = pick(x, (int)(B.n - 1 - col));
+      }
     }
-  }
 }
 
 // Storer s serves compute wave s.
-template <typename T, int W>
-__device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds* lds, int s, int lane,
-                                            const KArgs& a, uint32_t item) {
+template <typename T, int W, int R>
+__device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds* lds, WaveRings<R>* rings, int s,
+                                            int lane, const KArgs& a, uint32_t item) {
   const uint32_t SENT = Num<T>::SENT;
-  constexpr int PER = 1;
-  BandGeom B[PER];
-  bool active[PER];
-  int ks[PER];
-  glb_u32* qbase[PER][4];
+  const BandGeom B = band_geom<W, R>(g, band, s);
+  const bool active = B.row0 < B.m;
+  WaveLds& L = lds[s];
+  const unsigned char* hring = rings[s].hring;
+  int ks = 0;
+  glb_u32* qbase[R][4];
+  const int lq = io_quad(lane);
 #pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int w = PER * s + j;
-    B[j] = band_geom<W>(g, band, w < W ? w : 0);
-    active[j] = w < W && B[j].row0 < B[j].m;
-    ks[j] = 0;
+  for (int sr = 0; sr < R; ++sr)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int rho = 16 * i + (lane >> 2);
+      const int rho = R * (16 * i + (lane >> 2)) + sr;
       // Only dereferenced on the fast path, where the strip is full and the quad interior.
-      qbase[j][i] = G32((uint32_t*)g.out) + (B[j].row0 + rho) * g.ld_out + 4 * (lane & 3) - rho;
+      qbase[sr][i] = G32((uint32_t*)g.out) + (B.row0 + rho) * g.ld_out + 4 * lq - rho;
     }
-  }
   // Handoff-row re-arming: only the storer of compute wave 0, only below band 0.
   const bool rearm_hand = s == 0 && band > 0;
   __amdgpu_buffer_rsrc_t hand_in =
       make_rsrc(g.hand + (band > 0 ? (int64_t)(band - 1) * g.hand_ld : 0), (uint32_t)(g.hand_ld * 4));
-  int hr = 60;
-  const int hand_end = B[0].T_END;
+  int hr = t_first(R);
+  const int hand_end = B.T_END;
+  const bool full_strip = B.row0 + 64 * R < B.m;
   Watch t_idle;
   uint32_t polls = 0;
   for (;;) {
     bool did = false, done = true;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      if (!active[j]) continue;
-      WaveLds& L = lds[PER * s + j];
+    if (active) {
       // Store every chunk the compute wave has finished (progress >= 16 (k+1), or the
       // end of the walk), then release their H slots at once.
       const int prog = (int)ld_ctl(&L.progress);
       CBAR();
-      const int k0 = ks[j];
-      while (ks[j] < B[j].NC && prog >= (16 * (ks[j] + 1) < B[j].T_END ? 16 * (ks[j] + 1) : B[j].T_END)) {
-        if (glb_u64* r = chunk_rec(a, item, W, PER * s + j, ks[j]))
+      const int k0 = ks;
+      while (ks < B.NC && prog >= (16 * (ks + 1) < B.T_END ? 16 * (ks + 1) : B.T_END)) {
+        if (glb_u64* r = chunk_rec(a, item, W, s, ks))
           if (lane == 0) r[6] = wall_clock64();
-        if (!store_interior(B[j], ks[j])) store_chunk(g, B[j], L, ks[j], lane);
-        else if (B[j].row0 + 64 < B[j].m) store_chunk_fast<false>(g, B[j], L, ks[j], lane, qbase[j]);
-        else store_chunk_fast<true>(g, B[j], L, ks[j], lane, qbase[j]);
-        ++ks[j];
+        if (!store_interior<R>(B, ks)) store_chunk<R>(g, B, hring, ks, lane);
+        else if (full_strip) store_chunk_fast<R, false>(g, B, hring, ks, lane, qbase);
+        else store_chunk_fast<R, true>(g, B, hring, ks, lane, qbase);
+        ++ks;
       }
-      if (ks[j] > k0) {
+      if (ks > k0) {
         __builtin_amdgcn_s_waitcnt(0xc07f);  // the ring reads are done before the slots are released
         CBAR();
-        if (lane == 0) st_ctl(&L.h_done, (uint32_t)(16 * ks[j]));
+        if (lane == 0) st_ctl(&L.h_done, (uint32_t)(16 * ks));
         if (a.ctrace && lane == 0) {
           const uint64_t now = wall_clock64();
-          for (int kk = k0; kk < ks[j]; ++kk)
-            if (glb_u64* r = chunk_rec(a, item, W, PER * s + j, kk)) r[7] = now;
+          for (int kk = k0; kk < ks; ++kk)
+            if (glb_u64* r = chunk_rec(a, item, W, s, kk)) r[7] = now;
         }
         did = true;
       }
-      if (ks[j] < B[j].NC) done = false;
+      if (ks < B.NC) done = false;
     }
     if (rearm_hand) {
       int fed = (int)ld_ctl(&lds[0].t_fed);
@@ -936,24 +1044,24 @@ __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds
   }
 }
 
-// Feed the T ring of compute wave 0 (positions 60 .. T_END) from the top
+// Feed the T ring of compute wave 0 (positions t_first(R) .. T_END) from the top
 // boundary (band 0) or from the handoff row of the band above, then pad it with
-// absent values up to t_pad_end(G), the last position the walk's chunks check.
+// absent values up to t_pad_end(G, R), the last position the walk's chunks check.
 //
 // The handoff row is polled with two loads in flight, issued about half a round
 // trip apart, so new quads are seen about half a round trip sooner than with one.
 // A poll covers the next SMALL quads while the producer is ahead of it by less than
 // that (the usual case); when a poll comes back wholly valid the producer is far
 // ahead and the next poll covers up to 64 quads.
-template <typename T, int RULE, int W>
+template <typename T, int RULE, int W, int R>
 __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds* lds, int lane, const KArgs& a) {
   const uint32_t SENT = Num<T>::SENT;
-  const BandGeom B = band_geom<W>(g, band, 0);
+  const BandGeom B = band_geom<W, R>(g, band, 0);
   WaveLds& L = lds[0];
-  int tw = 60;
+  int tw = t_first(R);
   Watch t_idle;
   uint32_t polls = 0;
-  const int t_pad = t_pad_end(B.G);
+  const int t_pad = t_pad_end(B.G, R);
   if (band == 0) {
     while (tw < t_pad) {
       int limit = (int)ld_ctl(&L.t_reset) + RING_T;
@@ -966,7 +1074,7 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
           u4 v;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const int64_t ti = (int64_t)p + e - 62;  // index into top[] (= column + 1)
+            const int64_t ti = (int64_t)p + e - (64 * R - 2);  // index into top[] (= column + 1)
             T val = Num<T>::template absent<RULE>();
             if (ti >= 0 && ti <= B.n) {
               if (g.top) val = GC<T>(g.top)[ti];
@@ -1085,12 +1193,13 @@ __device__ __forceinline__ Role role_of(int wave) {
   }
 }
 
-// Two waves per SIMD at most (the LDS rings allow two workgroups of one compute wave per
-// compute unit, or one of two), so up to 256 VGPRs each.  TR: the launch records
-// traces; without it every trace branch is compiled out of the walk.
-template <typename T, int RULE, int W, bool TR>
+// Two waves per SIMD at most (the LDS rings allow two workgroups of one compute wave of
+// one row per lane per compute unit, or one of two such waves or of one wave of two rows
+// per lane), so up to 256 VGPRs each.  TR: the launch records traces; without it every
+// trace branch is compiled out of the walk.
+template <typename T, int RULE, int W, int R, bool TR>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * waves_for(W), 64 * waves_for(W)),
-                          amdgpu_waves_per_eu(2, 2)))
+                          amdgpu_waves_per_eu(R == 2 ? 1 : 2, R == 2 ? 1 : 2)))
 void wf_sweep_kernel(KArgs a_in) {
   KArgs a = a_in;
   if (!TR) {
@@ -1099,6 +1208,7 @@ void wf_sweep_kernel(KArgs a_in) {
     a.ctrace_nc = 0;
   }
   __shared__ WaveLds lds[W];
+  __shared__ WaveRings<R> rings[W];
   __shared__ uint32_t s_item;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -1121,8 +1231,8 @@ void wf_sweep_kernel(KArgs a_in) {
         // only after it has validated the first quad (positions 60..63), so the storer
         // cannot re-arm, and the feeder cannot refill, that slot before it has been read.
         L.progress = (uint32_t)-16;
-        L.t_reset = 60;
-        L.t_fed = 60;
+        L.t_reset = t_first(R);
+        L.t_fed = t_first(R);
         L.abort = 0;
         L.tr_start = L.tr_first = L.tr_end = L.tr_wall = 0;
         L.tr_chunk_wait = L.tr_t_wait = L.tr_load_wait = 0;
@@ -1143,11 +1253,11 @@ void wf_sweep_kernel(KArgs a_in) {
     }
     if (role.kind == R_COMPUTE) {
       uint64_t* crec = a.ctrace ? a.ctrace + ((int64_t)t * W + role.strip) * a.ctrace_nc * CTRACE_WORDS : nullptr;
-      compute_band<T, RULE, W>(gd, band, lds, role.strip, lane, a, crec);
+      compute_band<T, RULE, W, R>(gd, band, lds, rings, role.strip, lane, a, crec);
     }
-    else if (role.kind == R_LOADER) loader_band<W>(gd, band, lds, role.strip, lane, a, t);
-    else if (role.kind == R_STORER) storer_band<T, W>(gd, band, lds, role.strip, lane, a, t);
-    else feeder_band<T, RULE, W>(gd, band, lds, lane, a);
+    else if (role.kind == R_LOADER) loader_band<W, R>(gd, band, lds, rings, role.strip, lane, a, t);
+    else if (role.kind == R_STORER) storer_band<T, W, R>(gd, band, lds, rings, role.strip, lane, a, t);
+    else feeder_band<T, RULE, W, R>(gd, band, lds, lane, a);
     __syncthreads();
     if (a.trace && role.kind == R_COMPUTE && lane == 0) {
       const WaveLds& L = lds[role.strip];
@@ -1180,22 +1290,22 @@ __global__ void noalloc_prep_kernel(uint32_t* ctl, uint32_t reset_error, uint32_
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) hand[i] = sent;
 }
 
-template <typename T, int RULE, int W>
+template <typename T, int RULE, int W, int R>
 hipError_t launch_t(int nwg, const KArgs& args, hipStream_t stream) {
   if (args.trace || args.ctrace)
-    hipLaunchKernelGGL((wf_sweep_kernel<T, RULE, W, true>), dim3(nwg), dim3(64 * waves_for(W)), 0, stream, args);
+    hipLaunchKernelGGL((wf_sweep_kernel<T, RULE, W, R, true>), dim3(nwg), dim3(64 * waves_for(W)), 0, stream, args);
   else
-    hipLaunchKernelGGL((wf_sweep_kernel<T, RULE, W, false>), dim3(nwg), dim3(64 * waves_for(W)), 0, stream, args);
+    hipLaunchKernelGGL((wf_sweep_kernel<T, RULE, W, R, false>), dim3(nwg), dim3(64 * waves_for(W)), 0, stream, args);
   return hipGetLastError();
 }
 
+// Band shapes: W compute waves of R rows per lane (64 R W rows per band).
 template <typename T, int RULE>
-hipError_t launch_w(int W, int nwg, const KArgs& args, hipStream_t stream) {
-  switch (W) {
-    case 1: return launch_t<T, RULE, 1>(nwg, args, stream);
-    case 2: return launch_t<T, RULE, 2>(nwg, args, stream);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_w(int W, int R, int nwg, const KArgs& args, hipStream_t stream) {
+  if (W == 1 && R == 1) return launch_t<T, RULE, 1, 1>(nwg, args, stream);
+  if (W == 2 && R == 1) return launch_t<T, RULE, 2, 1>(nwg, args, stream);
+  if (W == 1 && R == 2) return launch_t<T, RULE, 1, 2>(nwg, args, stream);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -1218,11 +1328,15 @@ hipError_t noalloc_scratch(uint32_t** ptr) {
   return e;
 }
 
-size_t lds_bytes(int W) { return sizeof(WaveLds) * (size_t)W + 16; }
+size_t lds_bytes(int W, int R) {
+  return (sizeof(WaveLds) + (size_t)(C_SLOTS + H_SLOTS) * R * SLAB) * (size_t)W + 16;
+}
 
-hipError_t launch_sweep(int dtype, int rule, int W, int nwg, const KArgs& args, hipStream_t stream) {
-  if (dtype == 0) return rule == 0 ? launch_w<float, 0>(W, nwg, args, stream) : launch_w<float, 1>(W, nwg, args, stream);
-  if (dtype == 1) return rule == 0 ? launch_w<int32_t, 0>(W, nwg, args, stream) : launch_w<int32_t, 1>(W, nwg, args, stream);
+hipError_t launch_sweep(int dtype, int rule, int W, int R, int nwg, const KArgs& args, hipStream_t stream) {
+  if (dtype == 0)
+    return rule == 0 ? launch_w<float, 0>(W, R, nwg, args, stream) : launch_w<float, 1>(W, R, nwg, args, stream);
+  if (dtype == 1)
+    return rule == 0 ? launch_w<int32_t, 0>(W, R, nwg, args, stream) : launch_w<int32_t, 1>(W, R, nwg, args, stream);
   return hipErrorInvalidValue;
 }
 

@@ -204,29 +204,47 @@ wf_status wfh::check_problem(const wf_problem* p, int64_t idx) {
 }
 
 static wf_status check_tuning(const wf_tuning& t) {
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 3; ++i)
     if (t.reserved[i] != 0) return fail(WF_EINVAL, "wf_tuning.reserved must be 0");
   if (t.waves_per_wg < 0 || t.waves_per_wg > 2) return fail(WF_EINVAL, "waves_per_wg must be 0, 1 or 2");
+  if (t.rows_per_lane < 0 || t.rows_per_lane > 2) return fail(WF_EINVAL, "rows_per_lane must be 0, 1 or 2");
+  if (t.waves_per_wg == 2 && t.rows_per_lane == 2)
+    return fail(WF_EUNSUPPORTED, "two compute waves of two rows per lane do not fit the LDS");
   if (t.max_wgs < 0 || t.order < 0 || t.order > 2 || t.use_graph < -1 || t.use_graph > 1)
     return fail(WF_EINVAL, "bad tuning value");
   return WF_OK;
 }
 
 // ------------------------------------------------------------ configuration
-int wfh::choose_waves(int64_t m) {
-  // Bands of 64*W rows.  One strip per workgroup, spread over the compute units, is
-  // fastest for a single grid (compute waves sharing a compute unit slow each other
-  // more than the cheaper LDS handoff between them saves).
+int wfh::choose_shape(int64_t m) {
+  // One compute wave of one row per lane per workgroup, spread over the compute units.
+  // Two rows per lane halve the bands (and the handoffs between workgroups on the
+  // critical path), but measured at 16384 x 16384 each step of the walk then costs about
+  // 50 ns instead of 31 (the wave is bound by the instructions it issues, not by the
+  // chain's latency), so the walk is slower overall: 1.92 ms against 1.55 ms.
   (void)m;
   return 1;
 }
 
-// The LDS rings of one compute wave take about 66 KB of a compute unit's 160 KB.
-int wfh::wgs_per_cu(int W) { return W >= 2 ? 1 : 2; }
+// The LDS rings of one compute wave of one row per lane take about 66 KB of a compute
+// unit's 160 KB, so two such workgroups fit; the other shapes take twice that.
+int wfh::wgs_per_cu(int bs) { return bs == 1 ? 2 : 1; }
+
+hipError_t wfh::launch_shape(int dtype, int rule, int bs, int nwg, const KArgs& args, hipStream_t stream) {
+  return launch_sweep(dtype, rule, shape_waves(bs), shape_rows_per_lane(bs), nwg, args, stream);
+}
+
+// Band shape of explicit tuning values (0 = automatic for that field).
+static int shape_of_tuning(const wf_tuning& t, int64_t m) {
+  if (t.waves_per_wg == 0 && t.rows_per_lane == 0) return choose_shape(m);
+  if (t.waves_per_wg == 2) return 2;
+  if (t.rows_per_lane == 2) return 3;
+  return 1;
+}
 
 uint32_t wfh::sentinel_of(int dtype) { return dtype == WF_F32 ? SENT_F32 : SENT_I32; }
 
-GridDesc wfh::make_desc(const wf_problem* p, int W, uint32_t* hand) {
+GridDesc wfh::make_desc(const wf_problem* p, int bs, uint32_t* hand) {
   GridDesc d;
   std::memset(&d, 0, sizeof d);
   d.cost = p->cost;
@@ -241,15 +259,15 @@ GridDesc wfh::make_desc(const wf_problem* p, int W, uint32_t* hand) {
   d.n = p->n;
   d.ld_cost = p->ld_cost;
   d.ld_out = p->mode == WF_MODE_FULL ? p->ld_out : 0;
-  d.hand_ld = hand_ld_for(p->n);
+  d.hand_ld = hand_ld_for(p->n, shape_rows_per_lane(bs));
   d.mode = p->mode;
-  d.nbands = (int32_t)((p->m + 64 * W - 1) / (64 * W));
+  d.nbands = (int32_t)((p->m + shape_rows(bs) - 1) / shape_rows(bs));
   return d;
 }
 
-size_t wfh::hand_elems(const wf_problem* p, int W) {
-  const int64_t nb = (p->m + 64 * W - 1) / (64 * W);
-  return nb > 1 ? (size_t)(nb - 1) * (size_t)hand_ld_for(p->n) : 0;
+size_t wfh::hand_elems(const wf_problem* p, int bs) {
+  const int64_t nb = (p->m + shape_rows(bs) - 1) / shape_rows(bs);
+  return nb > 1 ? (size_t)(nb - 1) * (size_t)hand_ld_for(p->n, shape_rows_per_lane(bs)) : 0;
 }
 
 KArgs wfh::base_args(wf_ctx* ctx, uint32_t* ctl, int64_t nitems) {
@@ -265,7 +283,8 @@ KArgs wfh::base_args(wf_ctx* ctx, uint32_t* ctl, int64_t nitems) {
 
 // ------------------------------------------------------------ tuning cache
 // WF_TUNE_CACHE names a JSON file holding the autotuner's choices per shape class:
-//   {"version": 1, "entries": [{"class": "...", "W": 1, "order": 2, "wgs": 512, "ms": 3.8}, ...]}
+//   {"version": 2, "entries": [{"class": "...", "shape": 3, "order": 2, "wgs": 256, "ms": 3.8}, ...]}
+// (shape: the band shape, see wf_host.h).
 static void load_tune_cache(wf_ctx* ctx) {
   std::ifstream f(ctx->tune_file);
   if (!f) return;
@@ -296,13 +315,13 @@ static void load_tune_cache(wf_ctx* ctx) {
     const size_t end = t.find('}', at);
     if (end == std::string::npos) break;
     std::string cls;
-    double W = 0, order = 0, wgs = 0, ms = 0;
-    if (field(at, "class", end, &cls, nullptr) && field(at, "W", end, nullptr, &W) &&
+    double bs = 0, order = 0, wgs = 0, ms = 0;
+    if (field(at, "class", end, &cls, nullptr) && field(at, "shape", end, nullptr, &bs) &&
         field(at, "order", end, nullptr, &order) && field(at, "wgs", end, nullptr, &wgs)) {
       field(at, "ms", end, nullptr, &ms);
-      if ((W == 1 || W == 2) && (order == 1 || order == 2) && wgs >= 0) {
+      if ((bs >= 1 && bs <= SHAPE_MAX) && (order == 1 || order == 2) && wgs >= 0) {
         TuneEntry e;
-        e.W = (int)W;
+        e.bs = (int)bs;
         e.order = (int)order;
         e.wgs = (int)wgs;
         e.ms = ms;
@@ -319,10 +338,10 @@ static void save_tune_cache(const wf_ctx* ctx) {
   {
     std::ofstream f(tmp);
     if (!f) return;
-    f << "{\"version\": 1, \"entries\": [";
+    f << "{\"version\": 2, \"entries\": [";
     bool first = true;
     for (const auto& kv : ctx->tuned) {
-      f << (first ? "\n" : ",\n") << "  {\"class\": \"" << kv.first << "\", \"W\": " << kv.second.W
+      f << (first ? "\n" : ",\n") << "  {\"class\": \"" << kv.first << "\", \"shape\": " << kv.second.bs
         << ", \"order\": " << kv.second.order << ", \"wgs\": " << kv.second.wgs << ", \"ms\": " << kv.second.ms << "}";
       first = false;
     }
@@ -462,27 +481,27 @@ static wf_status report_sticky(wf_ctx* ctx) {
 }
 
 // One grid, one launch, at W compute waves per workgroup.
-static wf_status solve_one(wf_ctx* ctx, const wf_problem* p, int W, int max_wgs, hipStream_t stream) {
+static wf_status solve_one(wf_ctx* ctx, const wf_problem* p, int bs, int max_wgs, hipStream_t stream) {
   Slot* s = nullptr;
   wf_status st = acquire_slot(ctx, &s);
   if (st != WF_OK) return st;
-  st = ensure_hand(*s, hand_elems(p, W), sentinel_of(p->dtype), stream);
+  st = ensure_hand(*s, hand_elems(p, bs), sentinel_of(p->dtype), stream);
   if (st != WF_OK) return st;
   KArgs a = base_args(ctx, s->ctl, 0);
-  a.g0 = make_desc(p, W, s->hand);
+  a.g0 = make_desc(p, bs, s->hand);
   a.nitems = a.g0.nbands;
-  const int resident = ctx->num_cus * wgs_per_cu(W);
+  const int resident = ctx->num_cus * wgs_per_cu(bs);
   int nwg = (int)std::min<int64_t>(a.nitems, resident);
   if (max_wgs > 0) nwg = std::min(nwg, max_wgs);
   // Optional trace (profiling hook): WF_TRACE_FILE=<path> makes wf_solve synchronous
   // and writes TRACE_WORDS uint64 per (band, compute wave) to <path>.
   const char* trace_file = std::getenv("WF_TRACE_FILE");
   uint64_t* trace = nullptr;
-  const size_t trace_words = (size_t)a.nitems * W * TRACE_WORDS;
+  const size_t trace_words = (size_t)a.nitems * shape_waves(bs) * TRACE_WORDS;
   // With WF_TRACE_CHUNKS=1 it also writes CTRACE_WORDS uint64 per (band, compute wave, chunk).
-  const int64_t nc = ((4 * groups_for(p->n) + 15) / 16 + CTRACE_EVERY - 1) / CTRACE_EVERY;
+  const int64_t nc = ((4 * groups_for(p->n, shape_rows_per_lane(bs)) + 15) / 16 + CTRACE_EVERY - 1) / CTRACE_EVERY;
   const bool chunks = trace_file && *trace_file && std::getenv("WF_TRACE_CHUNKS");
-  const size_t ctrace_words = chunks ? (size_t)a.nitems * W * (size_t)nc * CTRACE_WORDS : 0;
+  const size_t ctrace_words = chunks ? (size_t)a.nitems * shape_waves(bs) * (size_t)nc * CTRACE_WORDS : 0;
   uint64_t* ctrace = nullptr;
   if (trace_file && *trace_file) {
     WF_HIP(hipMalloc(&trace, trace_words * sizeof(uint64_t)));
@@ -496,7 +515,7 @@ static wf_status solve_one(wf_ctx* ctx, const wf_problem* p, int W, int max_wgs,
     }
   }
   WF_HIP(launch_fill_u32(s->ctl, 0u, CTL_WORDS, stream));
-  WF_HIP(launch_sweep(p->dtype, p->rule, W, nwg, a, stream));
+  WF_HIP(launch_shape(p->dtype, p->rule, bs, nwg, a, stream));
   if (trace) {
     std::vector<uint64_t> host(trace_words), chost(ctrace_words);
     WF_HIP(hipMemcpyAsync(host.data(), trace, trace_words * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
@@ -506,7 +525,7 @@ static wf_status solve_one(wf_ctx* ctx, const wf_problem* p, int W, int max_wgs,
     WF_HIP(hipFree(trace));
     if (ctrace) WF_HIP(hipFree(ctrace));
     if (FILE* f = std::fopen(trace_file, "wb")) {
-      const uint64_t hdr[6] = {(uint64_t)a.nitems, (uint64_t)W, (uint64_t)TRACE_WORDS, (uint64_t)nwg,
+      const uint64_t hdr[6] = {(uint64_t)a.nitems, (uint64_t)shape_waves(bs), (uint64_t)TRACE_WORDS, (uint64_t)nwg,
                                (uint64_t)(ctrace ? nc : 0), (uint64_t)CTRACE_WORDS};
       std::fwrite(hdr, sizeof hdr, 1, f);
       std::fwrite(host.data(), sizeof(uint64_t), host.size(), f);
@@ -531,8 +550,8 @@ static wf_status solve_entry(wf_ctx* ctx, const wf_problem* p, const wf_tuning* 
   st = report_sticky(ctx);
   if (st != WF_OK) return st;
   if (p->m == 0 || p->n == 0) return WF_OK;
-  const int W = tun.waves_per_wg ? tun.waves_per_wg : choose_waves(p->m);
-  return solve_one(ctx, p, W, tun.max_wgs, (hipStream_t)stream_);
+  const int bs = shape_of_tuning(tun, p->m);
+  return solve_one(ctx, p, bs, tun.max_wgs, (hipStream_t)stream_);
 }
 
 extern "C" wf_status wf_solve(wf_ctx* ctx, const wf_problem* p, void* stream) {
@@ -552,8 +571,8 @@ extern "C" wf_status wf_solve_noalloc(wf_ctx* ctx, const wf_problem* p, void* st
   wf_status st = check_problem(p, -1);
   if (st != WF_OK) return st;
   if (!ctx->noalloc) return fail(WF_EHIP, "the context has no fixed workspace");
-  const int W = 1;
-  const size_t need = hand_elems(p, W);
+  const int bs = choose_shape(p->m);
+  const size_t need = hand_elems(p, bs);
   if (p->m > 0 && p->n > 0 && need > ctx->noalloc->hand_cap) {
     char msg[200];
     snprintf(msg, sizeof msg, "problem needs %lld bytes of handoff rows; the fixed workspace holds %lld "
@@ -569,12 +588,12 @@ extern "C" wf_status wf_solve_noalloc(wf_ctx* ctx, const wf_problem* p, void* st
   Slot& s = *ctx->noalloc;
   hipStream_t stream = (hipStream_t)stream_;
   KArgs a = base_args(ctx, s.ctl, 0);
-  a.g0 = make_desc(p, W, s.hand);
+  a.g0 = make_desc(p, bs, s.hand);
   a.nitems = a.g0.nbands;
-  const int nwg = (int)std::min<int64_t>(a.nitems, (int64_t)ctx->num_cus * wgs_per_cu(W));
+  const int nwg = (int)std::min<int64_t>(a.nitems, (int64_t)ctx->num_cus * wgs_per_cu(bs));
   WF_HIP(launch_noalloc_prep(s.ctl, s.needs_rearm, s.hand, sentinel_of(p->dtype), (int64_t)need, stream));
   s.needs_rearm = false;
-  WF_HIP(launch_sweep(p->dtype, p->rule, W, nwg, a, stream));
+  WF_HIP(launch_shape(p->dtype, p->rule, bs, nwg, a, stream));
   return finish_launch(s, stream);
 }
 
@@ -597,7 +616,7 @@ extern "C" wf_status wf_solve_each(wf_ctx* ctx, const wf_problem* ps, int64_t co
   if (st != WF_OK) return st;
   for (int64_t i = 0; i < count; ++i) {
     if (ps[i].m == 0 || ps[i].n == 0) continue;
-    st = solve_one(ctx, &ps[i], choose_waves(ps[i].m), 0, (hipStream_t)streams[i % nstreams]);
+    st = solve_one(ctx, &ps[i], choose_shape(ps[i].m), 0, (hipStream_t)streams[i % nstreams]);
     if (st != WF_OK) return st;
   }
   return WF_OK;
@@ -615,7 +634,7 @@ static uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
 
 // Grids in work order (largest first, so long critical paths start early) and the
 // (grid, band) work list: grid-major (order 1) or band-interleaved (order 2).
-static void build_work(const wf_problem* ps, int64_t count, int W, int order, std::vector<int64_t>& perm,
+static void build_work(const wf_problem* ps, int64_t count, int bs, int order, std::vector<int64_t>& perm,
                        std::vector<Item>& items, std::vector<size_t>& hand_off, size_t& hand_total) {
   perm.clear();
   items.clear();
@@ -629,8 +648,8 @@ static void build_work(const wf_problem* ps, int64_t count, int W, int order, st
   int64_t max_bands = 0;
   for (size_t gi = 0; gi < perm.size(); ++gi) {
     hand_off[gi] = hand_total;
-    hand_total += hand_elems(&ps[perm[gi]], W);
-    nb[gi] = (int32_t)((ps[perm[gi]].m + 64 * W - 1) / (64 * W));
+    hand_total += hand_elems(&ps[perm[gi]], bs);
+    nb[gi] = (int32_t)((ps[perm[gi]].m + shape_rows(bs) - 1) / shape_rows(bs));
     max_bands = std::max<int64_t>(max_bands, nb[gi]);
   }
   if (order == 2) {
@@ -643,20 +662,20 @@ static void build_work(const wf_problem* ps, int64_t count, int W, int order, st
   }
 }
 
-static int batch_wgs(const wf_ctx* ctx, int W, int64_t nitems, int max_wgs) {
-  int nwg = (int)std::min<int64_t>(nitems, (int64_t)ctx->num_cus * wgs_per_cu(W));
+static int batch_wgs(const wf_ctx* ctx, int bs, int64_t nitems, int max_wgs) {
+  int nwg = (int)std::min<int64_t>(nitems, (int64_t)ctx->num_cus * wgs_per_cu(bs));
   if (max_wgs > 0) nwg = std::min(nwg, max_wgs);
   return std::max(nwg, 1);
 }
 
 // A batched launch that is not kept for replay (autotuning trials, plain launches).
-static wf_status batched_once(wf_ctx* ctx, const wf_problem* ps, int64_t count, int W, int order, int max_wgs,
+static wf_status batched_once(wf_ctx* ctx, const wf_problem* ps, int64_t count, int bs, int order, int max_wgs,
                               hipStream_t stream) {
   std::vector<int64_t> perm;
   std::vector<Item> items;
   std::vector<size_t> hand_off;
   size_t hand_total = 0;
-  build_work(ps, count, W, order, perm, items, hand_off, hand_total);
+  build_work(ps, count, bs, order, perm, items, hand_off, hand_total);
   if (items.empty()) return WF_OK;
   Slot* s = nullptr;
   wf_status st = acquire_slot(ctx, &s);
@@ -666,7 +685,7 @@ static wf_status batched_once(wf_ctx* ctx, const wf_problem* ps, int64_t count, 
   if (st == WF_OK) st = ensure_buf(&s->items, &s->items_cap, items.size());
   if (st != WF_OK) return st;
   std::vector<GridDesc> descs(perm.size());
-  for (size_t gi = 0; gi < perm.size(); ++gi) descs[gi] = make_desc(&ps[perm[gi]], W, s->hand + hand_off[gi]);
+  for (size_t gi = 0; gi < perm.size(); ++gi) descs[gi] = make_desc(&ps[perm[gi]], bs, s->hand + hand_off[gi]);
   WF_HIP(hipMemcpyAsync(s->grids, descs.data(), descs.size() * sizeof(GridDesc), hipMemcpyHostToDevice, stream));
   WF_HIP(hipMemcpyAsync(s->items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, stream));
   WF_HIP(hipStreamSynchronize(stream));  // the host arrays must outlive the copies
@@ -674,7 +693,7 @@ static wf_status batched_once(wf_ctx* ctx, const wf_problem* ps, int64_t count, 
   a.grids = s->grids;
   a.items = s->items;
   WF_HIP(launch_fill_u32(s->ctl, 0u, CTL_WORDS, stream));
-  WF_HIP(launch_sweep(ps[perm[0]].dtype, ps[perm[0]].rule, W, batch_wgs(ctx, W, a.nitems, max_wgs), a, stream));
+  WF_HIP(launch_shape(ps[perm[0]].dtype, ps[perm[0]].rule, bs, batch_wgs(ctx, bs, a.nitems, max_wgs), a, stream));
   return finish_launch(*s, stream);
 }
 
@@ -690,9 +709,9 @@ static std::vector<int64_t> shape_of(const wf_problem* ps, int64_t count) {
 
 // A cached batch plan: found by the batch's shapes and configuration, replayed with
 // two lanes in turn.  Its tables are rebuilt only when the problem array changes.
-static wf_status batched_plan(wf_ctx* ctx, const wf_problem* ps, int64_t count, int W, int order, int max_wgs,
+static wf_status batched_plan(wf_ctx* ctx, const wf_problem* ps, int64_t count, int bs, int order, int max_wgs,
                               bool use_graph, hipStream_t stream) {
-  const uint64_t cfg[5] = {(uint64_t)count, (uint64_t)W, (uint64_t)order, (uint64_t)max_wgs, (uint64_t)use_graph};
+  const uint64_t cfg[5] = {(uint64_t)count, (uint64_t)bs, (uint64_t)order, (uint64_t)max_wgs, (uint64_t)use_graph};
   uint64_t h = fnv1a(1469598103934665603ull, cfg, sizeof cfg);
   const int dtype = ps[0].dtype, rule = ps[0].rule;
   const uint64_t dr[2] = {(uint64_t)dtype, (uint64_t)rule};
@@ -700,7 +719,7 @@ static wf_status batched_plan(wf_ctx* ctx, const wf_problem* ps, int64_t count, 
   BatchPlanEntry* e = nullptr;
   // Fast path: the very problem array of the plan's last launch.
   for (auto& p : ctx->plans)
-    if (p->probs.size() == (size_t)count && p->W == W && p->order == order && p->use_graph == use_graph &&
+    if (p->probs.size() == (size_t)count && p->bs == bs && p->order == order && p->use_graph == use_graph &&
         p->dtype == dtype && p->rule == rule &&
         std::memcmp(p->probs.data(), ps, (size_t)count * sizeof(wf_problem)) == 0) {
       e = p.get();
@@ -710,7 +729,7 @@ static wf_status batched_plan(wf_ctx* ctx, const wf_problem* ps, int64_t count, 
     std::vector<int64_t> shape = shape_of(ps, count);
     h = fnv1a(h, shape.data(), shape.size() * sizeof(int64_t));
     for (auto& p : ctx->plans)
-      if (p->hash == h && p->shape == shape && p->W == W && p->order == order && p->use_graph == use_graph &&
+      if (p->hash == h && p->shape == shape && p->bs == bs && p->order == order && p->use_graph == use_graph &&
           p->dtype == dtype && p->rule == rule && p->probs.size() == (size_t)count) {
         e = p.get();
         break;
@@ -727,13 +746,13 @@ static wf_status batched_plan(wf_ctx* ctx, const wf_problem* ps, int64_t count, 
       std::unique_ptr<BatchPlanEntry> n(new BatchPlanEntry);
       n->hash = h;
       n->shape = std::move(shape);
-      n->W = W;
+      n->bs = bs;
       n->order = order;
       n->dtype = dtype;
       n->rule = rule;
       n->use_graph = use_graph;
-      build_work(ps, count, W, order, n->perm, n->items, n->hand_off, n->hand_total);
-      n->nwg = batch_wgs(ctx, W, (int64_t)n->items.size(), max_wgs);
+      build_work(ps, count, bs, order, n->perm, n->items, n->hand_off, n->hand_total);
+      n->nwg = batch_wgs(ctx, bs, (int64_t)n->items.size(), max_wgs);
       ctx->plans.push_back(std::move(n));
       e = ctx->plans.back().get();
     }
@@ -765,7 +784,7 @@ static wf_status batched_plan(wf_ctx* ctx, const wf_problem* ps, int64_t count, 
     L.items_loaded = true;
   }
   std::vector<GridDesc> descs(e->perm.size());
-  for (size_t gi = 0; gi < e->perm.size(); ++gi) descs[gi] = make_desc(&ps[e->perm[gi]], W, s.hand + e->hand_off[gi]);
+  for (size_t gi = 0; gi < e->perm.size(); ++gi) descs[gi] = make_desc(&ps[e->perm[gi]], bs, s.hand + e->hand_off[gi]);
   if (L.descs.size() != descs.size() ||
       std::memcmp(L.descs.data(), descs.data(), descs.size() * sizeof(GridDesc)) != 0) {
     if (!L.staging) WF_HIP(hipHostMalloc((void**)&L.staging, descs.size() * sizeof(GridDesc), hipHostMallocDefault));
@@ -783,7 +802,7 @@ static wf_status batched_plan(wf_ctx* ctx, const wf_problem* ps, int64_t count, 
       hipError_t err = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
       if (err == hipSuccess) {
         launch_fill_u32(s.ctl, 0u, CTL_WORDS, cap);
-        launch_sweep(dtype, rule, W, e->nwg, a, cap);
+        launch_shape(dtype, rule, bs, e->nwg, a, cap);
         err = hipStreamEndCapture(cap, &L.graph);
       }
       if (err == hipSuccess) err = hipGraphInstantiate(&L.exec, L.graph, nullptr, nullptr, 0);
@@ -793,7 +812,7 @@ static wf_status batched_plan(wf_ctx* ctx, const wf_problem* ps, int64_t count, 
     WF_HIP(hipGraphLaunch(L.exec, stream));
   } else {
     WF_HIP(launch_fill_u32(s.ctl, 0u, CTL_WORDS, stream));
-    WF_HIP(launch_sweep(dtype, rule, W, e->nwg, a, stream));
+    WF_HIP(launch_shape(dtype, rule, bs, e->nwg, a, stream));
   }
   return finish_launch(s, stream);
 }
@@ -817,8 +836,9 @@ static std::string shape_class(const wf_problem* ps, int64_t count) {
   return buf;
 }
 
-// Candidates: waves per workgroup x work order x workgroup count (every resident
-// workgroup, or half of them).  Each runs twice back to back on `stream`, the second
+// Candidates: band shape (64-row bands; 128-row bands of two chained compute waves;
+// 128-row bands of one wave with two rows per lane) x work order x workgroup count
+// (every resident workgroup, or half of them).  Each runs twice back to back on `stream`, the second
 // run timed with events (its host set-up overlaps the first run on the device).
 static wf_status autotune(wf_ctx* ctx, const wf_problem* ps, int64_t count, int max_wgs, hipStream_t stream,
                           TuneEntry* out) {
@@ -834,17 +854,17 @@ static wf_status autotune(wf_ctx* ctx, const wf_problem* ps, int64_t count, int 
   TuneEntry best;
   best.ms = -1;
   wf_status st = WF_OK;
-  for (int W = 1; W <= 2 && st == WF_OK; ++W) {
-    const int resident = ctx->num_cus * wgs_per_cu(W);
+  for (int bs = 1; bs <= SHAPE_MAX && st == WF_OK; ++bs) {
+    const int resident = ctx->num_cus * wgs_per_cu(bs);
     const int wg_opts[2] = {max_wgs > 0 ? std::min(max_wgs, resident) : resident,
                             std::max(1, (max_wgs > 0 ? std::min(max_wgs, resident) : resident) / 2)};
     for (int order = 1; order <= 2 && st == WF_OK; ++order) {
       for (int wi = 0; wi < 2 && st == WF_OK; ++wi) {
         const int wgs = wg_opts[wi];
-        st = batched_once(ctx, ps, count, W, order, wgs, stream);
+        st = batched_once(ctx, ps, count, bs, order, wgs, stream);
         if (st != WF_OK) break;
         hipError_t e = hipEventRecord(e0, stream);
-        if (e == hipSuccess) st = batched_once(ctx, ps, count, W, order, wgs, stream);
+        if (e == hipSuccess) st = batched_once(ctx, ps, count, bs, order, wgs, stream);
         if (st == WF_OK && e == hipSuccess) e = hipEventRecord(e1, stream);
         if (st == WF_OK && e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -855,7 +875,7 @@ static wf_status autotune(wf_ctx* ctx, const wf_problem* ps, int64_t count, int 
         if (st != WF_OK) break;
         if (best.ms < 0 || ms < best.ms) {
           best.ms = ms;
-          best.W = W;
+          best.bs = bs;
           best.order = order;
           best.wgs = wgs;
         }
@@ -895,19 +915,20 @@ extern "C" wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t
   bool any = false;
   for (int64_t i = 0; i < count && !any; ++i) any = ps[i].m > 0 && ps[i].n > 0;
   if (!any) return WF_OK;
-  int W = tun.waves_per_wg, order = tun.order, wgs = tun.max_wgs;
-  if (W == 0 && order == 0 && tun.use_graph != -1) {
+  int bs = 0, order = tun.order, wgs = tun.max_wgs;
+  if (tun.waves_per_wg != 0 || tun.rows_per_lane != 0) bs = shape_of_tuning(tun, 0);
+  if (bs == 0 && order == 0 && tun.use_graph != -1) {
     TuneEntry te;
     st = autotune(ctx, ps, count, tun.max_wgs, stream, &te);
     if (st != WF_OK) return st;
-    W = te.W;
+    bs = te.bs;
     order = te.order;
     wgs = te.wgs;
   }
-  if (W == 0) W = 1;
+  if (bs == 0) bs = 1;
   if (order == 0) order = 1;
-  if (tun.use_graph == 1) return batched_plan(ctx, ps, count, W, order, wgs, true, stream);
-  return batched_once(ctx, ps, count, W, order, wgs, stream);
+  if (tun.use_graph == 1) return batched_plan(ctx, ps, count, bs, order, wgs, true, stream);
+  return batched_once(ctx, ps, count, bs, order, wgs, stream);
 }
 
 // ------------------------------------------------------------- measurement

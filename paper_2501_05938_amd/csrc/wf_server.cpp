@@ -161,9 +161,11 @@ Layout layout_of(const wf_request& r) {
   at += round_up(m * 4);
   L.final_cell = at;
   at += ALIGN;
-  // Handoff rows for the finest banding (64 rows per band), so any launch width fits.
+  // Handoff rows for the finest banding (64 rows per band), so any band shape fits: at
+  // 128-row bands there are at most half as many boundaries, each 64 positions longer
+  // (and a handoff row is at least 64 positions).
   const int64_t nb = (r.m + 63) / 64;
-  L.hand_n = nb > 1 ? (size_t)(nb - 1) * (size_t)hand_ld_for(r.n) : 0;
+  L.hand_n = nb > 1 ? (size_t)(nb - 1) * (size_t)hand_ld_for(r.n, 1) : 0;
   L.hand = at;
   at += round_up(std::max<size_t>(L.hand_n, 1) * 4);
   L.total = at;
@@ -258,7 +260,7 @@ struct wf_server {
   void admit(double t);
   bool try_admit(Req& q, uint64_t ticket, double t);
   bool launch_one(std::unique_lock<std::mutex>& lk);
-  wf_status enqueue(LaunchSlot& L, std::vector<Req*>& batch, int W, int dtype, int rule);
+  wf_status enqueue(LaunchSlot& L, std::vector<Req*>& batch, int bs, int dtype, int rule);
   wf_status start_copy(Req& q, Copy* c);
 };
 
@@ -401,7 +403,7 @@ void wf_server::admit(double t) {
   }
 }
 
-wf_status wf_server::enqueue(LaunchSlot& L, std::vector<Req*>& batch, int W, int dtype, int rule) {
+wf_status wf_server::enqueue(LaunchSlot& L, std::vector<Req*>& batch, int bs, int dtype, int rule) {
   hipStream_t s = L.stream;
   // Host inputs without copy streams go through the slot's pinned staging buffer on the
   // launch stream: a copy from pageable memory is staged synchronously by the runtime in
@@ -434,7 +436,7 @@ wf_status wf_server::enqueue(LaunchSlot& L, std::vector<Req*>& batch, int W, int
   // Descriptors, largest grid first, and the grid-major work list.
   std::sort(batch.begin(), batch.end(), [](const Req* a, const Req* b) { return a->r.m * a->r.n > b->r.m * b->r.n; });
   size_t nitems = 0;
-  for (Req* q : batch) nitems += (size_t)((q->r.m + 64 * W - 1) / (64 * W));
+  for (Req* q : batch) nitems += (size_t)((q->r.m + shape_rows(bs) - 1) / shape_rows(bs));
   wf_status st = grow_host(&L.h_grids, &L.h_grids_cap, batch.size());
   if (st == WF_OK) st = grow_host(&L.h_items, &L.h_items_cap, nitems);
   if (st == WF_OK) st = grow_dev(&L.d_grids, &L.grids_cap, batch.size());
@@ -457,7 +459,7 @@ wf_status wf_server::enqueue(LaunchSlot& L, std::vector<Req*>& batch, int W, int
     p.last_row = q->last_row;
     p.last_col = q->last_col;
     p.final_cell = q->final_cell;
-    GridDesc d = make_desc(&p, W, q->hand);
+    GridDesc d = make_desc(&p, bs, q->hand);
     L.h_grids[gi] = d;
     for (int b = 0; b < d.nbands; ++b) L.h_items[k++] = Item{(uint32_t)gi, (uint32_t)b};
   }
@@ -466,9 +468,9 @@ wf_status wf_server::enqueue(LaunchSlot& L, std::vector<Req*>& batch, int W, int
   KArgs a = base_args(ctx, L.ctl, (int64_t)nitems);
   a.grids = L.d_grids;
   a.items = L.d_items;
-  const int nwg = (int)std::min<int64_t>((int64_t)nitems, (int64_t)ctx->num_cus * wgs_per_cu(W));
+  const int nwg = (int)std::min<int64_t>((int64_t)nitems, (int64_t)ctx->num_cus * wgs_per_cu(bs));
   WF_HIP(launch_fill_u32(L.ctl, 0u, CTL_WORDS, s));
-  WF_HIP(launch_sweep(dtype, rule, W, nwg, a, s));
+  WF_HIP(launch_shape(dtype, rule, bs, nwg, a, s));
   WF_HIP(hipMemcpyAsync(L.host_err, L.ctl + CTL_ERROR, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   WF_HIP(hipEventRecord(L.done, s));
   return WF_OK;
@@ -505,12 +507,12 @@ bool wf_server::launch_one(std::unique_lock<std::mutex>& lk) {
   L->busy = true;
   L->tickets = tickets;
   ++inflight;
-  const int W = choose_waves(max_m);
+  const int bs = choose_shape(max_m);
   const double t = now_s();
   for (Req* q : batch) q->t_launch = t;
   // Requests in `batch` are LAUNCHED: wf_release refuses them, so the pointers stay valid.
   lk.unlock();
-  wf_status st = enqueue(*L, batch, W, dtype, rule);
+  wf_status st = enqueue(*L, batch, bs, dtype, rule);
   const std::string msg = st == WF_OK ? std::string() : std::string(wf_last_error());
   lk.lock();
   if (st != WF_OK) {

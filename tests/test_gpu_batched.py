@@ -1,7 +1,8 @@
 """GPU parity of the batched sweep: many uneven grids in one persistent launch.
 
 Every grid of a batch must be bit-identical to the CPU oracle (fp32 / int32),
-for every configuration the autotuner can pick (waves per workgroup 1, 2;
+for every configuration the autotuner can pick (band shapes of one or two
+compute waves of one row per lane, or one wave of two rows per lane;
 grid-major and interleaved work order), on graph replay, and in edges mode.
 """
 import numpy as np
@@ -37,16 +38,16 @@ def _bits(t):
     return a.view(np.uint32) if a.dtype == np.float32 else a
 
 
-@pytest.mark.parametrize("W", [1, 2])
+@pytest.mark.parametrize("W,R", [(1, 1), (2, 1), (1, 2)])
 @pytest.mark.parametrize("order", [1, 2])
-def test_every_configuration(W, order):
-    print(f"[batched] W={W} order={order}", flush=True)
+def test_every_configuration(W, R, order):
+    print(f"[batched] W={W} R={R} order={order}", flush=True)
     shapes, hs, ds = _batch(40, 1, 700, seed=11)
-    outs = wf.solve_batched(ds, waves_per_wg=W, order=order, use_graph=0)
+    outs = wf.solve_batched(ds, waves_per_wg=W, rows_per_lane=R, order=order, use_graph=0)
     torch.cuda.synchronize()
     wf.check()
     for (m, n), h, o in zip(shapes, hs, outs):
-        assert np.array_equal(_bits(o), _expect(h, "min", "f32")), (m, n, W, order)
+        assert np.array_equal(_bits(o), _expect(h, "min", "f32")), (m, n, W, R, order)
 
 
 def test_autotuned_graph_replay_and_alone():

@@ -6,8 +6,9 @@ Bar: bit-exact for fp32 against the fp32 oracle loop (the result of
 bit-exact for int32; against the fp64 oracle every cell must satisfy
 |H32 - H64| <= gamma_{i+j+1} * |H64| (the rounding bound pinned in
 test_oracle_pins.py).  Shapes cover one row/column, several bands of every
-workgroup size (64, 128 and 256 rows), ragged tails and leading dimensions
-larger than n.
+band shape (64-row bands; 128-row bands of two compute waves chained through
+LDS, or of one wave whose lanes own two rows each), ragged tails and leading
+dimensions larger than n.
 """
 import os
 import sys
@@ -44,9 +45,10 @@ def _gamma_bound(H64):
     return k * U / (1 - k * U) * np.abs(H64)
 
 
-def _case(m, n, rule="min", dtype="f32", seed=1, explicit=False, ld_pad=0, pad_value=0, waves_per_wg=0):
+def _case(m, n, rule="min", dtype="f32", seed=1, explicit=False, ld_pad=0, pad_value=0, waves_per_wg=0,
+          rows_per_lane=0):
     print(f"[parity] m={m} n={n} rule={rule} dtype={dtype} seed={seed} explicit={explicit} ld_pad={ld_pad} "
-          f"pad_value={pad_value} W={waves_per_wg}", flush=True)
+          f"pad_value={pad_value} W={waves_per_wg} R={rows_per_lane}", flush=True)
     c = wfgen.cells(seed, m, n, dtype)
     top = left = None
     if explicit:
@@ -61,7 +63,8 @@ def _case(m, n, rule="min", dtype="f32", seed=1, explicit=False, ld_pad=0, pad_v
         cd = _dev(c)
         out = torch.full((m, n), float("nan") if dtype == "f32" else -7, dtype=cd.dtype, device=DEV)
     H = wf.solve(cd, out=out, rule=rule, top=None if top is None else _dev(top),
-                 left=None if left is None else _dev(left), waves_per_wg=waves_per_wg)
+                 left=None if left is None else _dev(left), waves_per_wg=waves_per_wg,
+                 rows_per_lane=rows_per_lane)
     got = _host(H)
     wf.check()
     if dtype == "f32":
@@ -125,6 +128,7 @@ def test_row_padding_holding_the_sentinel(m, n, dtype):
     pad = 0xFFFFFFFF if dtype == "f32" else 0x80000000
     _case(m, n, dtype=dtype, seed=9, ld_pad=5, pad_value=pad)
     _case(m, n, rule="max", dtype=dtype, seed=9, ld_pad=5, pad_value=pad, waves_per_wg=2)
+    _case(m, n, dtype=dtype, seed=9, ld_pad=5, pad_value=pad, rows_per_lane=1)
 
 
 @pytest.mark.parametrize("m,n", [(1, 1), (65, 65), (129, 300), (300, 513), (2100, 333), (1024, 1024)])
@@ -132,6 +136,31 @@ def test_row_padding_holding_the_sentinel(m, n, dtype):
 def test_two_compute_waves_per_workgroup(m, n, rule):
     """wf_solve_tuned with bands of 128 rows: two compute waves chained through LDS."""
     _case(m, n, rule=rule, seed=10, waves_per_wg=2)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 300), (63, 63), (64, 64), (65, 65), (127, 5), (128, 128), (129, 300),
+                                 (300, 513), (2100, 333), (1024, 1024), (4097, 65)])
+@pytest.mark.parametrize("rule", ["min", "max"])
+def test_one_row_per_lane(m, n, rule):
+    """wf_solve_tuned with 64-row bands given explicitly (the shape wf_solve picks)."""
+    _case(m, n, rule=rule, seed=12, rows_per_lane=1)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (2, 3), (63, 63), (64, 64), (65, 65), (127, 5), (128, 128), (129, 300),
+                                 (255, 700), (256, 256), (257, 1000), (2100, 333)])
+@pytest.mark.parametrize("dtype", ["f32", "i32"])
+def test_two_rows_per_lane(m, n, dtype):
+    """wf_solve_tuned with 128-row bands of one wave whose lanes own two rows, from one
+    row to several bands, with ragged last bands."""
+    _case(m, n, dtype=dtype, seed=13, rows_per_lane=2)
+    _case(m, n, rule="max", dtype=dtype, seed=14, explicit=True, rows_per_lane=2)
+
+
+def test_two_waves_of_two_rows_is_rejected():
+    a = torch.zeros((4, 4), dtype=torch.float32, device=DEV)
+    with pytest.raises(wf.WfError) as e:
+        wf.solve(a, waves_per_wg=2, rows_per_lane=2)
+    assert e.value.status == -8  # WF_EUNSUPPORTED
 
 
 def test_config_small_grid_1024_and_repeatability():
