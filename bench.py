@@ -2,7 +2,7 @@
 """Benchmark of the MI355X wavefront sweep.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-large] [--no-batched]
-                    [--no-serving] [--no-copy-serving] [--no-fp64] [--no-cpu]
+                    [--no-serving] [--no-copy-serving] [--no-fp64] [--no-dtw] [--no-cpu]
 
 One step = one sweep of the 16384 x 16384 fp32 grid (min rule, full output):
 one persistent kernel launch through the C ABI (wf_solve).  Inputs are
@@ -21,6 +21,9 @@ Prints ONE JSON line.  Besides the contract fields it carries
                 workload;
   large_edges:  the 65536 x 65536 grid in edges mode;
   fp64:         the 16384 x 16384 grid in fp64 (16 B per cell);
+  dtw:          dynamic time warping of two 16384-long sequences (inputs |x_i - y_j|
+                computed on the device), edges mode and full mode;
+  traceback:    the path back from the last cell of the 16384 x 16384 grid;
   batched:      4096 grids, m and n log-uniform in [64, 2048], one persistent
                 launch (replayed hipGraph) against 4096 separate launches on 1..32
                 streams, with the paper's stream-count model (Sections 2.3-2.4)
@@ -63,6 +66,7 @@ def parse():
     ap.add_argument("--no-model", action="store_true", help="skip the stream-count model calibration")
     ap.add_argument("--no-large", action="store_true", help="skip the 65536x65536 edges-mode run")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-dtw", action="store_true", help="skip dynamic time warping and the traceback")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -196,14 +200,10 @@ def large_edges(torch, wf, wfgen, steps=3):
 
 
 def fp64_leg(torch, wf, wfgen, steps=5):
-    """The 16384 x 16384 grid in fp64 (inputs widened from the fp32 generator): 16 B per
-    cell of algorithmic traffic."""
-    if not hasattr(wf, "DTYPES") or "f64" not in wf.DTYPES:
-        return {"error": "fp64 not built"}
-    c32 = torch.empty((M, N), dtype=torch.float32, device="cuda")
-    wfgen.fill_device(c32, seed=SEED)
-    c = c32.double()
-    del c32
+    """The 16384 x 16384 grid in fp64 (53-bit uniform [0, 1) inputs from the seeded
+    generator, filled on the device): 16 B per cell of algorithmic traffic."""
+    c = torch.empty((M, N), dtype=torch.float64, device="cuda")
+    wfgen.fill_device(c, seed=SEED)
     out = torch.empty_like(c)
     run = lambda: wf.solve(c, out=out)  # noqa: E731
     run()
@@ -220,6 +220,57 @@ def fp64_leg(torch, wf, wfgen, steps=5):
             "kernel_ms": kms, "cells_per_s": M * N / (kms * 1e-3),
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": alg, "bytes_per_cell": 16}}
+
+
+def dtw_leg(torch, wf, wfgen, step_ns, steps=5):
+    """Dynamic time warping of two 16384-long sequences (cell inputs |x_i - y_j| computed on
+    the device): edges mode (the distance and the last row / column; HBM traffic O(m + n),
+    so the bound is the walk's latency) and full mode (the whole cost matrix written:
+    4 B per cell)."""
+    x = torch.empty((1, M), dtype=torch.float32, device="cuda")
+    y = torch.empty((1, N), dtype=torch.float32, device="cuda")
+    wfgen.fill_device(x, seed=41)
+    wfgen.fill_device(y, seed=42)
+    x, y = x[0], y[0]
+    lr = torch.empty(N, device="cuda"); lc = torch.empty(M, device="cuda"); fc = torch.empty(1, device="cuda")
+    out = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    res = {"workload": "dynamic time warping of two 16384-long fp32 sequences (uniform [0,1), seeds 41 and 42)",
+           "steps": steps}
+    floor_ms = (M + N - 1) * step_ns * 1e-6
+    for mode in ("edges", "full"):
+        run = (lambda: wf.dtw(x, y, mode="edges", last_row=lr, last_col=lc, final_cell=fc)) if mode == "edges" \
+            else (lambda: wf.dtw(x, y, out=out))
+        run()
+        torch.cuda.synchronize()
+        wf.check()
+        kms = sum(time_events(torch, run, steps, torch.cuda.current_stream())) / steps
+        wf.check()
+        r = {"kernel_ms": kms, "cells_per_s": M * N / (kms * 1e-3),
+             "latency": {"bound": "latency", "floor_ms": floor_ms, "frac": floor_ms / kms}}
+        if mode == "full":
+            alg = 4.0 * M * N
+            r["roofline"] = {"bound": "hbm", "achieved": alg / (kms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, "bytes_per_cell": 4}
+        res[mode] = r
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
+def traceback_leg(torch, wf, cost, steps=3):
+    """The traceback of the 16384 x 16384 benchmark grid: one workgroup walks back from the
+    last cell through 64 x 64 blocks staged in LDS (a sequential path of up to m + n - 1
+    cells; latency-bound)."""
+    H = wf.solve(cost)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        path, ex = wf.traceback(H)  # waits for the path length
+        ts.append((time.perf_counter() - t0) * 1e3)
+    L = int(path.shape[0])
+    return {"workload": "traceback of the 16384x16384 min-rule grid (seed 2)", "path_cells": L,
+            "ms": median(ts), "ns_per_cell": median(ts) * 1e6 / L, "exit": [int(v) for v in ex.cpu().tolist()]}
 
 
 STREAMS = (1, 2, 4, 8, 16, 32)
@@ -617,6 +668,9 @@ def main():
         legs.append(("large_edges", lambda: large_edges(torch, wf, wfgen)))
     if not args.no_fp64:
         legs.append(("fp64", lambda: fp64_leg(torch, wf, wfgen)))
+    if not args.no_dtw:
+        legs.append(("dtw", lambda: dtw_leg(torch, wf, wfgen, step_ns)))
+        legs.append(("traceback", lambda: traceback_leg(torch, wf, cost)))
     if not args.no_batched:
         legs.append(("batched", lambda: batched(torch, wf, wfgen, args.batch_count, not args.no_model)))
     if not args.no_serving:

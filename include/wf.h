@@ -38,6 +38,11 @@
  *   WF_I32: int32 inputs and outputs, wrapping 32-bit addition; results are
  *   exact while every partial path sum stays inside (INT32_MIN, INT32_MAX).
  *   The value INT32_MIN is reserved (never a valid result).
+ *   WF_F64: float64 inputs and outputs, one IEEE round-to-nearest-even fp64
+ *   addition per cell, bit-identical to a sequential fp64 loop; the paper's own
+ *   computations are FP64 (its Section 2), FP32 its variant (Section 3.2).  fp64
+ *   grids use 64-row bands only, n and ld_cost at most 2^22, and are not served
+ *   by the server; 16 bytes of memory traffic per cell in FULL mode.
  *
  * MEMORY AND OWNERSHIP
  *   All data pointers in wf_problem are DEVICE pointers on the context's
@@ -80,16 +85,24 @@ enum {
   WF_EUNSUPPORTED = -8   /* valid but unsupported combination */
 };
 
-enum { WF_F32 = 0, WF_I32 = 1 };              /* element type of cost, top, left and outputs */
+enum { WF_F32 = 0, WF_I32 = 1, WF_F64 = 2 };  /* element type of cost, top, left and outputs */
 enum { WF_RULE_MIN = 0, WF_RULE_MAX = 1 };    /* op of the cell rule */
 enum { WF_MODE_FULL = 0, WF_MODE_EDGES = 1 }; /* FULL writes all of H; EDGES writes only last row/col/cell */
+/* wf_problem.flags.  WF_COST_ABSDIFF: dynamic time warping of two sequences.  The
+ * input of cell (i, j) is |seq_x[i] - seq_y[j]| (the difference rounded once in fp32;
+ * the absolute value is exact), computed on the device, so only the m + n sequence
+ * values are read from memory; cost and ld_cost are ignored.  WF_F32 only.  With
+ * the min rule and the default boundary, H[i][j] is the DTW distance of x[0..i] and
+ * y[0..j].  (The paper has no such workload: it is a second input of the same
+ * cell rule.) */
+enum { WF_COST_ABSDIFF = 1 };
 
 typedef struct wf_problem {
-  int64_t m, n;            /* grid rows and columns, >= 1 (0 means nothing to do); n <= 2^23 */
-  int32_t dtype;           /* WF_F32 or WF_I32 */
+  int64_t m, n;            /* grid rows and columns, >= 1 (0 means nothing to do); n <= 2^23 (2^22 for fp64) */
+  int32_t dtype;           /* WF_F32, WF_I32 or WF_F64 */
   int32_t rule;            /* WF_RULE_MIN or WF_RULE_MAX */
   int32_t mode;            /* WF_MODE_FULL or WF_MODE_EDGES */
-  int32_t flags;           /* must be 0 */
+  int32_t flags;           /* 0 or WF_COST_ABSDIFF */
   const void* cost;        /* device, m x n, row stride ld_cost elements; required */
   int64_t ld_cost;         /* >= n and <= 2^23 (WF_EUNSUPPORTED above) */
   void* out;               /* device, m x n, row stride ld_out; required in FULL mode, ignored in EDGES */
@@ -99,6 +112,8 @@ typedef struct wf_problem {
   void* last_row;          /* device, n values, or NULL (required in EDGES mode unless last_col or final_cell given) */
   void* last_col;          /* device, m values, or NULL */
   void* final_cell;        /* device, 1 value, or NULL */
+  const void* seq_x;       /* WF_COST_ABSDIFF: device, m values (else ignored) */
+  const void* seq_y;       /* WF_COST_ABSDIFF: device, n values (else ignored) */
 } wf_problem;
 
 typedef struct wf_tuning {
@@ -174,6 +189,23 @@ wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t count, con
  * give wrong results.  Order them on one stream. */
 #define WF_NOALLOC_SCRATCH_BYTES (32ll << 20)
 wf_status wf_solve_noalloc(wf_ctx* ctx, const wf_problem* p, void* stream);
+
+/* Traceback, the step after a sweep: the path of predecessor choices through a
+ * computed grid.  Reads p->out (FULL-mode H of an m x n problem, row stride
+ * p->ld_out), p->dtype, p->rule and p->top / p->left (the boundary the sweep used,
+ * or NULL for the default); cost and the edge outputs are not used.  Starting at
+ * (m-1, n-1) it repeatedly steps to the predecessor -- NW (i-1, j-1), N (i-1, j),
+ * W (i, j-1), boundary values standing in for predecessors outside the grid --
+ * whose value the rule selects (smallest for min, largest for max), the first of
+ * NW, N, W on equal values, and stops when that predecessor lies outside the grid.
+ * The paper states no traceback; the preference order is this library's reading.
+ * Writes to `path` (device, int32, 2 * (m + n) entries) the visited cells as (i, j)
+ * pairs, (m-1, n-1) first, followed by the outside predecessor the walk ended on
+ * ((-1, j), (i, -1) or (-1, -1)); writes the number of visited cells (at most
+ * m + n - 1) to `length` (device, one int64).  Asynchronous on `stream` like
+ * wf_solve; one workgroup walks the grid in 64 x 64 tiles staged in LDS.
+ * Errors: WF_EINVAL (m or n < 1, NULL out/path/length, ld_out < n). */
+wf_status wf_traceback(wf_ctx* ctx, const wf_problem* p, int32_t* path, int64_t* length, void* stream);
 
 /* Set the device watchdog of later launches on this context: a wait for a
  * neighbouring band that makes no progress for `ms` milliseconds (0 .. 3600000)

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libwf.so")
 WF_OK, WF_PENDING = 0, 1
 STATUS = {0: "WF_OK", 1: "WF_PENDING", -1: "WF_EINVAL", -2: "WF_ENOMEM", -3: "WF_E2BIG", -4: "WF_EHIP",
           -5: "WF_ETIMEDOUT", -6: "WF_ENOTFOUND", -7: "WF_ESHUTDOWN", -8: "WF_EUNSUPPORTED"}
-DTYPES = {"f32": 0, "i32": 1}
+DTYPES = {"f32": 0, "i32": 1, "f64": 2}
 RULES = {"min": 0, "max": 1}
 MODES = {"full": 0, "edges": 1}
 
@@ -43,7 +43,11 @@ class Problem(ctypes.Structure):
                 ("cost", ctypes.c_void_p), ("ld_cost", ctypes.c_int64),
                 ("out", ctypes.c_void_p), ("ld_out", ctypes.c_int64),
                 ("top", ctypes.c_void_p), ("left", ctypes.c_void_p),
-                ("last_row", ctypes.c_void_p), ("last_col", ctypes.c_void_p), ("final_cell", ctypes.c_void_p)]
+                ("last_row", ctypes.c_void_p), ("last_col", ctypes.c_void_p), ("final_cell", ctypes.c_void_p),
+                ("seq_x", ctypes.c_void_p), ("seq_y", ctypes.c_void_p)]
+
+
+COST_ABSDIFF = 1  # WF_COST_ABSDIFF
 
 
 class Tuning(ctypes.Structure):
@@ -100,6 +104,7 @@ _SIGS = {
     "wf_solve_batched": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.c_int64, ctypes.POINTER(Tuning), _P]),
     "wf_solve_tuned": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(Tuning), _P]),
     "wf_solve_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(Problem), _P]),
+    "wf_traceback": (ctypes.c_int, [_P, ctypes.POINTER(Problem), _P, _P, _P]),
     "wf_solve_each": (ctypes.c_int, [_P, ctypes.POINTER(Problem), ctypes.c_int64, ctypes.POINTER(_P), ctypes.c_int32]),
     "wf_set_watchdog": (ctypes.c_int, [_P, ctypes.c_int64]),
     "wf_check": (ctypes.c_int, [_P]),
@@ -179,7 +184,9 @@ def _dtype_of(t):
         return "f32"
     if t.dtype == torch.int32:
         return "i32"
-    raise TypeError("cost must be float32 or int32")
+    if t.dtype == torch.float64:
+        return "f64"
+    raise TypeError("cost must be float32, float64 or int32")
 
 
 def _ld(t, n):
@@ -242,6 +249,64 @@ def solve(cost, out=None, rule: str = "min", top=None, left=None, mode: str = "f
     if mode == "full":
         return out
     return last_row, last_col, final_cell
+
+
+def dtw(x, y, out=None, rule: str = "min", mode: str = "full", stream=None, last_row=None, last_col=None,
+        final_cell=None, waves_per_wg: int = 0, max_wgs: int = 0, rows_per_lane: int = 0):
+    """Dynamic time warping of two float32 device sequences x (m) and y (n): the sweep with
+    cell inputs |x[i] - y[j]| computed on the device (WF_COST_ABSDIFF), so only the
+    sequences are read.  mode="full" returns D (m x n); mode="edges" returns
+    (last_row, last_col, final_cell).  Asynchronous on `stream`."""
+    import torch
+    if not (x.is_cuda and y.is_cuda) or x.dtype != torch.float32 or y.dtype != torch.float32:
+        raise ValueError("x and y must be float32 device tensors")
+    if x.dim() != 1 or y.dim() != 1 or not x.is_contiguous() or not y.is_contiguous():
+        raise ValueError("x and y must be contiguous vectors")
+    m, n = x.numel(), y.numel()
+    if mode == "full" and out is None:
+        out = torch.empty((m, n), dtype=torch.float32, device=x.device)
+    if mode == "edges":
+        last_row = torch.empty(n, dtype=torch.float32, device=x.device) if last_row is None else last_row
+        last_col = torch.empty(m, dtype=torch.float32, device=x.device) if last_col is None else last_col
+        final_cell = torch.empty(1, dtype=torch.float32, device=x.device) if final_cell is None else final_cell
+    p = Problem()
+    p.m, p.n = m, n
+    p.dtype, p.rule, p.mode, p.flags = DTYPES["f32"], RULES[rule], MODES[mode], COST_ABSDIFF
+    p.cost, p.ld_cost = None, n
+    p.seq_x, p.seq_y = x.data_ptr(), y.data_ptr()
+    if out is not None:
+        p.out, p.ld_out = out.data_ptr(), _ld(out, n)
+    for name, t in (("last_row", last_row), ("last_col", last_col), ("final_cell", final_cell)):
+        if t is not None:
+            setattr(p, name, t.data_ptr())
+    lib = load_library()
+    if waves_per_wg or max_wgs or rows_per_lane:
+        t = Tuning()
+        t.waves_per_wg, t.max_wgs, t.rows_per_lane = waves_per_wg, max_wgs, rows_per_lane
+        _check(lib.wf_solve_tuned(context(x.device.index), ctypes.byref(p), ctypes.byref(t), _stream_ptr(stream)))
+    else:
+        _check(lib.wf_solve(context(x.device.index), ctypes.byref(p), _stream_ptr(stream)))
+    if mode == "full":
+        return out
+    return last_row, last_col, final_cell
+
+
+def traceback(H, rule: str = "min", top=None, left=None, stream=None):
+    """wf_traceback: the path of predecessor choices through the computed grid H (device,
+    float32 or int32; top/left: the boundary the sweep used).  Returns (path, exit): path
+    is an (L, 2) int32 device tensor of visited cells, (m-1, n-1) first; exit the (2,)
+    outside predecessor the walk ended on.  Waits for the stream to read L."""
+    import torch
+    m, n = H.shape
+    p = make_problem(H, H, rule, top, left)
+    buf = torch.empty((m + n, 2), dtype=torch.int32, device=H.device)
+    length = torch.empty(1, dtype=torch.int64, device=H.device)
+    _check(load_library().wf_traceback(context(H.device.index), ctypes.byref(p), buf.data_ptr(),
+                                       length.data_ptr(), _stream_ptr(stream)))
+    if stream is not None:
+        stream.synchronize()
+    L = int(length.item())
+    return buf[:L], buf[L]
 
 
 NOALLOC_SCRATCH_BYTES = 32 << 20  # WF_NOALLOC_SCRATCH_BYTES

@@ -98,8 +98,8 @@ inline int shape_rows_per_lane(int bs) { return bs == 3 ? 2 : 1; }
 inline int shape_rows(int bs) { return 64 * shape_waves(bs) * shape_rows_per_lane(bs); }
 // Band shape for a single grid with m rows.
 int choose_shape(int64_t m);
-// Resident workgroups per compute unit at band shape bs.
-int wgs_per_cu(int bs);
+// Resident workgroups per compute unit at band shape bs (fp64 workgroups take 98 KB of LDS).
+int wgs_per_cu(int bs, int dtype);
 // Launch of the sweep kernel at band shape bs.
 hipError_t launch_shape(int dtype, int rule, int bs, int nwg, const wfk::KArgs& args, hipStream_t stream);
 // Handoff sentinel of a dtype.

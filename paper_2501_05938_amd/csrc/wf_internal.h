@@ -20,8 +20,11 @@ struct GridDesc {
   void* last_col;
   void* final_cell;
   uint32_t* hand;
+  const void* sx;         // kind 1: the sequences whose absolute differences are the cell inputs
+  const void* sy;
   int64_t m, n, ld_cost, ld_out, hand_ld;
   int32_t mode, nbands;
+  int32_t kind, pad;      // kind 0: inputs read from `cost`; 1: |sx[i] - sy[j]|
 };
 
 // One work item: band `band` of grid `grid`.
@@ -76,10 +79,13 @@ __host__ __device__ inline int64_t groups_for(int64_t n, int R) { return (n + 64
 __host__ __device__ inline int64_t hand_ld_for(int64_t n, int R) { return ((4 * groups_for(n, R)) + 63) / 64 * 64; }
 
 // Launch helpers implemented in wf_kernel.hip.
-// dtype 0 = f32, 1 = i32; rule 0 = min, 1 = max; W compute waves per workgroup of R rows
-// per lane: (W, R) = (1, 1), (2, 1) or (1, 2).
+// dtype 0 = f32, 1 = i32, 2 = f64; rule 0 = min, 1 = max; W compute waves per workgroup of
+// R rows per lane: (W, R) = (1, 1), (2, 1) or (1, 2); f64 only (1, 1).
 hipError_t launch_sweep(int dtype, int rule, int W, int R, int nwg, const KArgs& args, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t stream);
+// Traceback of a computed grid (see wf_traceback): dtype 0 = f32, 1 = i32, 2 = f64.
+hipError_t launch_traceback(int dtype, int rule, const void* H, int64_t ld, int64_t m, int64_t n, const void* top,
+                            const void* left, int32_t* path, int64_t* length, hipStream_t stream);
 // LDS bytes per workgroup (for occupancy decisions).
 size_t lds_bytes(int W, int R);
 

@@ -46,6 +46,7 @@
 #include "wf_internal.h"
 
 #include <stddef.h>
+#include <type_traits>
 
 namespace wfk {
 namespace {
@@ -139,6 +140,11 @@ template <> struct Num<int32_t> {
   __device__ static int32_t add(int32_t a, int32_t b) { return (int32_t)((uint32_t)a + (uint32_t)b); }
 };
 
+// fp64 (its own sweep kernel below; the traceback uses the absent value).
+template <> struct Num<double> {
+  template <int RULE> __device__ static double absent() { return RULE == 0 ? __builtin_inf() : -__builtin_inf(); }
+};
+
 // N for every lane: lane r receives lane r-1's `src`; lane 0 keeps `old`.
 // Shift acc one lane down within each row of 16 lanes (lane i takes lane i+1) and put
 // this lane's h where no source lane exists (lanes 15, 31, 47, 63).  After j calls,
@@ -203,7 +209,8 @@ __device__ __forceinline__ uint32_t ld_dev(uint32_t* p) {
 }
 
 // Abort the whole launch: raise the workgroup flag and the device-wide flag.
-__device__ __forceinline__ void raise_abort(WaveLds* lds, const KArgs& a) {
+template <class WL>
+__device__ __forceinline__ void raise_abort(WL* lds, const KArgs& a) {
   st_ctl(&lds[0].abort, 1u);
   __hip_atomic_store(G32(a.ctl + CTL_ERROR), (uint32_t)DEV_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(G32(a.ctl + CTL_ABORT), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -238,8 +245,8 @@ struct Watch {
 // Compute waves watch only the workgroup flag (no global loads on their path, so the
 // hot loop never waits on vector-memory counters); IO waves also poll the device flag
 // and relay it into the workgroup flag.
-template <bool DEVICE_FLAG, class F>
-__device__ __forceinline__ bool wait_until(F&& cond, WaveLds* lds, const KArgs& a) {
+template <bool DEVICE_FLAG, class F, class WL>
+__device__ __forceinline__ bool wait_until(F&& cond, WL* lds, const KArgs& a) {
   if (cond()) return true;
   Watch w;
   uint32_t polls = 0;
@@ -282,7 +289,8 @@ __device__ __forceinline__ bool aborting(WaveLds* lds, uint32_t* ctl, uint64_t w
 // Rare path of an inline spin, called every few thousand polls.  Returns the start
 // of the idle period (taking it now when t0 is 0), or 0 when the wait must end: the
 // launch is aborting, or the wait has outlasted the watchdog (then it raises the abort).
-__device__ __noinline__ uint64_t spin_check(WaveLds* lds, uint32_t* ctl, uint64_t watchdog_ticks, uint64_t t0) {
+template <class WL>
+__device__ __noinline__ uint64_t spin_check(WL* lds, uint32_t* ctl, uint64_t watchdog_ticks, uint64_t t0) {
   if (ld_ctl(&lds[0].abort)) return 0;
   const uint64_t now = wall_clock64() | 1u;
   if (t0 == 0) return now;
@@ -357,12 +365,16 @@ __device__ __forceinline__ void snap_ctl(WaveLds& L, WaveLds* C, CtlSnap& s) {
 // without branches): when the producer is not that far yet, the chunk waits for the
 // chunk's last quad, which the producer writes after the others.
 // KIND 0: the first 4 R chunks, where rows left of column 0 keep their boundary value;
-// KIND 1: every later chunk.  The T ring is fed past the band's last T position with
+// KIND 1: every later chunk.  MASK: KIND 0 chunks select the kept value per cell; without
+// it (floating point, default left boundary, no row padding) a cell left of column 0 is
+// computed like any other: its own and its upper neighbours' values are then all
+// "absent" (infinite), the finite input added to an infinity gives the same infinity,
+// and every such cell holds the absent value, which is its boundary value.  The T ring is fed past the band's last T position with
 // absent values, so KIND 1 chunks read and check all four quads; groups past the last
 // one (g >= G) compute cells right of the grid, which nothing stores or reads.
 // CONS: 0 = no consumer, 1 = the next compute wave (LDS), 2 = the next band (global
 // handoff row).
-template <typename T, int RULE, int R, int KIND, int CONS>
+template <typename T, int RULE, int R, int KIND, int CONS, bool MASK>
 __device__ __forceinline__ void compute_chunk(
     int k, int G, int gT, int NCc, WaveLds* lds, WaveLds& L, WaveLds* C,
     __amdgpu_buffer_rsrc_t hand_out, const lds_u8* const (&cq)[4], lds_u8* const (&hq)[4], lds_u8* ct_base,
@@ -478,7 +490,7 @@ __device__ __forceinline__ void compute_chunk(
       for (int sr = R - 1; sr >= 1; --sr)
         Hn[sr] = Num<T>::add(from_bits<T>(cc[sr][q][e]), Num<T>::template op3<RULE>(H[sr - 1], Hp[sr - 1], H[sr]));
       Hn[0] = Num<T>::add(from_bits<T>(cc[0][q][e]), Num<T>::template op3<RULE>(N, Np, H[0]));
-      if (KIND == 0) {
+      if (KIND == 0 && MASK) {
         // rows left of column 0 keep the left boundary
 #pragma unroll
         for (int sr = 0; sr < R; ++sr) Hn[sr] = (4 * g + e < R * lane + sr) ? H[sr] : Hn[sr];
@@ -513,7 +525,7 @@ __device__ __forceinline__ void compute_chunk(
   }
 }
 
-template <typename T, int RULE, int R, int CONS>
+template <typename T, int RULE, int R, int CONS, bool MASK>
 __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLds& L, WaveLds* C,
                                              __amdgpu_buffer_rsrc_t hand_out, const lds_u8* const (&cq)[4],
                                              lds_u8* const (&hq)[4], int lane, const T (&Hinit)[R], const KArgs& a,
@@ -527,7 +539,9 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   if (Num<T>::probe(tprev) == Num<T>::SENT)
     tprev = wait_quad<T>(L8(L.tring) + TF * 4, lds, a.ctl, a.watchdog_ticks, nullptr);
   if (a.trace && lane == 0) L.tr_first = __builtin_readcyclecounter();
-  T Np = from_bits<T>(tprev.z);
+  // NW of step 0: the corner for lane 0; for the other lanes the row above's column -1,
+  // which lies left of the grid (absent by default; selected away when masked).
+  T Np = lane == 0 ? from_bits<T>(tprev.z) : Num<T>::template absent<RULE>();
   uint32_t tprev_w = tprev.w;
   if (lane == 0) {
     const u4 s4 = {Num<T>::SENT, Num<T>::SENT, Num<T>::SENT, Num<T>::SENT};
@@ -546,7 +560,7 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   CtlSnap snap;
   snap_ctl<CONS>(L, C, snap);
 #define WF_CHUNK(KIND, KK, CUR_C, CUR_T, NXT_C, NXT_T)                                                         \
-  compute_chunk<T, RULE, R, KIND, CONS>(KK, G, gT, NCc, lds, L, C, hand_out, cq, hq, ct_base, lane63, lane,    \
+  compute_chunk<T, RULE, R, KIND, CONS, MASK>(KK, G, gT, NCc, lds, L, C, hand_out, cq, hq, ct_base, lane63, lane,  \
                                         CUR_C, CUR_T, NXT_C, NXT_T, tprev_w, H, Hp, Np, snap, a, crec)
   int k = 0;
   // The first 4 R chunks (groups 0 .. 16 R - 1, where rows left of column 0 are masked;
@@ -613,13 +627,23 @@ __device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLd
     cq[q] = L8(rings[w].cring) + quad_off(lane, q);
     hq[q] = L8(rings[w].hring) + quad_off(lane, q);
   }
+  // Cells left of column 0 need no per-cell selection when they stay at the absent
+  // value by themselves (see compute_chunk): floating point, default left boundary, and
+  // no row padding (the inputs read for them are then the finite tail of the row above).
+  const bool unmasked = !std::is_integral<T>::value && g.left == nullptr && g.ld_cost == n;
   if (lds_consumer) {
-    compute_walk<T, RULE, R, 1>(G, gT, lds, L, &lds[w + 1], __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec);
+    compute_walk<T, RULE, R, 1, true>(G, gT, lds, L, &lds[w + 1], __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec);
   } else if (glob_consumer) {
     __amdgpu_buffer_rsrc_t hand_out = make_rsrc(g.hand + (int64_t)band * g.hand_ld, (uint32_t)(g.hand_ld * 4));
-    compute_walk<T, RULE, R, 2>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec);
+    if (unmasked)
+      compute_walk<T, RULE, R, 2, false>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec);
+    else
+      compute_walk<T, RULE, R, 2, true>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec);
   } else {
-    compute_walk<T, RULE, R, 0>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec);
+    if (unmasked)
+      compute_walk<T, RULE, R, 0, false>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec);
+    else
+      compute_walk<T, RULE, R, 0, true>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec);
   }
   if (a.trace && lane == 0) L.tr_end = __builtin_readcyclecounter();
 }
@@ -717,8 +741,8 @@ struct LoaderLanes {
 // Idle step of a polling IO wave: sleep, then check abort and the watchdog.
 // Only waves that may load from memory (DEVICE_FLAG) poll the device-wide flag;
 // the others watch the workgroup flag, which those relay.
-template <bool DEVICE_FLAG>
-__device__ __forceinline__ bool io_idle(WaveLds* lds, const KArgs& a, Watch& w, uint32_t& polls) {
+template <bool DEVICE_FLAG, class WL>
+__device__ __forceinline__ bool io_idle(WL* lds, const KArgs& a, Watch& w, uint32_t& polls) {
   __builtin_amdgcn_s_sleep(1);
   if (ld_ctl(&lds[0].abort)) return false;
   if (DEVICE_FLAG && (++polls & 255u) == 0u && ld_dev(a.ctl + CTL_ABORT)) {
@@ -736,11 +760,66 @@ __device__ __forceinline__ bool io_idle(WaveLds* lds, const KArgs& a, Watch& w, 
 // row 16i + L/4, whose swizzle is ((L/4) >> 1) & 3 whatever i.
 __device__ __forceinline__ int io_quad(int lane) { return (lane & 3) ^ ((lane >> 3) & 3); }
 
+// Loader of a dynamic-time-warping band (GridDesc::kind 1, fp32): the inputs of chunk
+// k are computed rather than loaded.  Lane L covers the same (row, quad) cells as in
+// the DMA path and writes |x[row] - y[col]| for its four columns into the same slot
+// position; x[row] stays in registers for the whole band, and y is read at the column
+// clamped into [0, n), the value of a column outside the grid then replaced by 0 (those
+// cells are never used).  Only the m + n sequence values are read from memory.
+template <int W, int R>
+__device__ __forceinline__ void absdiff_loader_band(const GridDesc& g, const BandGeom& B, WaveLds& L,
+                                                    unsigned char* cring, WaveLds* lds, int lane, const KArgs& a) {
+  const int lq = io_quad(lane);
+  float xv[R][4];
+  int rho[R][4];
+#pragma unroll
+  for (int s = 0; s < R; ++s)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      rho[s][i] = R * (16 * i + (lane >> 2)) + s;
+      const int64_t row = B.row0 + rho[s][i];
+      xv[s][i] = row < B.m ? GC<float>(g.sx)[row] : 0.0f;
+    }
+  const __attribute__((address_space(1))) float* ys = GC<float>(g.sy);
+  Watch t_idle;
+  uint32_t polls = 0;
+  for (int k = 0; k < B.NC; ++k) {
+    // The slot last held chunk k - C_SLOTS: wait until the compute wave is past it.
+    while ((int)ld_ctl(&L.progress) < 16 * (k - C_SLOTS + 1))
+      if (!io_idle<false>(lds, a, t_idle, polls)) return;
+    t_idle.reset();
+    lds_u8* slot = L8(cring) + (k % C_SLOTS) * (R * SLAB);
+#pragma unroll
+    for (int s = 0; s < R; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int col = 16 * k + 4 * lq - rho[s][i];
+        u4 v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int cc = col + e;
+          const bool in = cc >= 0 && cc < B.n;
+          const float y = in ? ys[in ? cc : 0] : 0.0f;
+          const float d = xv[s][i] - y;  // one fp32 rounding; the absolute value is exact
+          v[e] = bits(__builtin_fabsf(d));
+        }
+        lds_st4(slot + SLAB * s + 1024 * i + 16 * lane, v);
+      }
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the slot is written before it is published
+    CBAR();
+    if (lane == 0) st_ctl(&L.c_ready, (uint32_t)(k + 1));
+  }
+}
+
 template <int W, int R>
 __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds* lds, WaveRings<R>* rings, int w,
                                             int lane, const KArgs& a, uint32_t item) {
   const BandGeom B = band_geom<W, R>(g, band, w);
   if (B.row0 >= B.m) return;
+  if (g.kind == 1) {
+    absdiff_loader_band<W, R>(g, B, lds[w], rings[w].cring, lds, lane, a);
+    return;
+  }
   WaveLds& L = lds[w];
   unsigned char* cring = rings[w].cring;
   // Elements from the strip's first row to the end of the grid.
@@ -1279,6 +1358,560 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
 }
 
+// ======================================================================= fp64
+// The fp64 sweep: bands of 64 rows, one compute wave per workgroup (lane r owns row r),
+// and the same four roles as the 4-byte kernel.  A chunk of 16 positions of one row is
+// 128 bytes: two slab rows of 64 bytes (slab h holds positions 8h .. 8h + 7, a quad two
+// positions), so a chunk slot is two slabs and the loader and storer move 16 bytes per
+// lane as before.
+//
+// Top-boundary and handoff positions travel encoded in 16 bytes each: the high word,
+// the low word's upper and lower 16 bits, the high word again.  Every word of a written
+// position then differs from the all-ones sentinel (a high word of all ones is a NaN,
+// which neither an input nor a sum of finite inputs and infinities produces), so a
+// reader checks each 32-bit word on its own: an access that races a write may see any
+// mix of old and new words, and the position is taken only when all four are new.
+// The bottom row is handed on by the storer, which reads it from the H ring after
+// storing a chunk, so the walk issues no memory instructions at all.
+constexpr int RT64 = 128;       // positions of the fp64 T ring (16 bytes each)
+constexpr int H64_SLOTS = 4;    // chunk slots of the fp64 H ring
+
+__device__ __forceinline__ u4 enc64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t hi = (uint32_t)(b >> 32), lo = (uint32_t)b;
+  return u4{hi, lo >> 16, lo & 0xFFFFu, hi};
+}
+__device__ __forceinline__ double dec64(const u4& q) {
+  return __builtin_bit_cast(double, ((uint64_t)q.x << 32) | (uint64_t)((q.y << 16) | q.z));
+}
+// SENT_F32 iff some word of the position is still the sentinel.
+__device__ __forceinline__ uint32_t probe_pos(const u4& q) {
+  const uint32_t a = q.x > q.y ? q.x : q.y, b = q.z > q.w ? q.z : q.w;
+  return a > b ? a : b;
+}
+template <int RULE> __device__ __forceinline__ double absent64() {
+  return RULE == 0 ? __builtin_inf() : -__builtin_inf();
+}
+template <int RULE> __device__ __forceinline__ double op3_64(double a, double b, double c) {
+  if constexpr (RULE == 0) return __builtin_fmin(__builtin_fmin(a, b), c);
+  else return __builtin_fmax(__builtin_fmax(a, b), c);
+}
+// N for every lane: lane r receives lane r-1's `src`; lane 0 keeps `old`.
+__device__ __forceinline__ double dpp_shr1_64(double old, double src) {
+  const uint64_t o = __builtin_bit_cast(uint64_t, old), s = __builtin_bit_cast(uint64_t, src);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)s, 0x138, 0xf, 0xf, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(s >> 32), 0x138, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+struct alignas(16) WaveLds64 {
+  u4 tring[RT64];     // encoded T positions
+  uint32_t c_ready;   // chunks of c committed to the c ring (loader -> compute)
+  uint32_t h_done;    // positions of H stored out of the H ring (storer -> compute)
+  uint32_t progress;  // (signed) position of the chunk being computed (compute -> IO)
+  uint32_t t_reset;   // T positions below this are re-armed (compute -> feeder)
+  uint32_t abort;     // workgroup abort flag
+  uint32_t t_fed;     // T positions written by the feeder (feeder -> storer)
+  uint32_t pad[2];
+};
+struct alignas(16) WaveRings64 {
+  unsigned char cring[C_SLOTS * 2 * SLAB];
+  unsigned char hring[H64_SLOTS * 2 * SLAB];
+};
+
+// LDS offset of row r's position p (0..15) of a chunk inside a slot.
+__device__ __forceinline__ int pos_off64(int r, int p) { return (p >> 3) * SLAB + quad_off(r, (p & 7) >> 1) + 8 * (p & 1); }
+
+// Chunk k of the walk (16 steps): wait for the c chunk, a free H slot and the 16 T
+// positions the chunk needs, re-arm those T slots, then run the 16 steps.
+template <int RULE, int KIND>
+__device__ __forceinline__ void compute_chunk64(int k, int NC, WaveLds64& L, WaveLds64* lds, const lds_u8* cslot0,
+                                                lds_u8* hslot0, int lane, double& H, double& Np, double& tprev,
+                                                const KArgs& a) {
+  const int pos = CHUNK * k;
+  CBAR();
+  if (lane == 0) st_ctl(&L.progress, (uint32_t)pos);
+  const int need_h = pos + CHUNK - H64_SLOTS * CHUNK;
+  wait_until<false>([&] { return (int)ld_ctl(&L.c_ready) >= k + 1 && (int)ld_ctl(&L.h_done) >= need_h; }, lds, a);
+  CBAR();
+  // T positions pos + 64 .. pos + 79: lane j < 16 holds position pos + 64 + j.
+  const int tslot = (pos + 64 + (lane & 15)) & (RT64 - 1);
+  u4 tq = lds_ld4_fresh(L8(&L.tring[tslot]));
+  {
+    uint64_t t0 = 0;
+    uint32_t spins = 0;
+    for (;;) {
+      const bool bad = lane < 16 && probe_pos(tq) == SENT_F32;
+      if (__builtin_amdgcn_ballot_w64(bad) == 0ull) break;
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 2047u) == 0u && (t0 = spin_check(lds, a.ctl, a.watchdog_ticks, t0)) == 0) break;
+      tq = lds_ld4_fresh(L8(&L.tring[tslot]));
+    }
+  }
+  const double tv = dec64(tq);  // lane j: position pos + 64 + j
+  CBAR();
+  // Re-arm the chunk's T slots (every lane holds its value in a register now).
+  if (lane < 16) lds_st4(L8(&L.tring[tslot]), u4{SENT_F32, SENT_F32, SENT_F32, SENT_F32});
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  CBAR();
+  if (lane == 0) st_ctl(&L.t_reset, (uint32_t)(pos + 80));
+  const lds_u8* cs = cslot0 + (k % C_SLOTS) * (2 * SLAB);
+  lds_u8* hs = hslot0 + (k % H64_SLOTS) * (2 * SLAB);
+  double c[16];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u4 v = lds_ld4(cs + h * SLAB + quad_off(lane, q));
+      c[8 * h + 2 * q] = __builtin_bit_cast(double, ((uint64_t)v.y << 32) | v.x);
+      c[8 * h + 2 * q + 1] = __builtin_bit_cast(double, ((uint64_t)v.w << 32) | v.z);
+    }
+  double hv[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    // Lane 0's N at step pos + s is the row above at column pos + s: position pos + s + 63.
+    const double tn = s == 0 ? tprev : __builtin_bit_cast(double, (uint64_t)__builtin_amdgcn_readlane(
+                                                                       (int)(__builtin_bit_cast(uint64_t, tv) >> 32), s - 1)
+                                                                       << 32 |
+                                                                   (uint32_t)__builtin_amdgcn_readlane(
+                                                                       (int)(uint32_t)__builtin_bit_cast(uint64_t, tv), s - 1));
+    const double N = dpp_shr1_64(tn, H);
+    double Hn = c[s] + op3_64<RULE>(N, Np, H);
+    if (KIND == 0) Hn = (pos + s < lane) ? H : Hn;  // rows left of column 0 keep the left boundary
+    Np = N;
+    H = Hn;
+    hv[s] = H;
+  }
+  tprev = __builtin_bit_cast(double, (uint64_t)__builtin_amdgcn_readlane((int)(__builtin_bit_cast(uint64_t, tv) >> 32), 15)
+                                         << 32 |
+                                     (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)__builtin_bit_cast(uint64_t, tv), 15));
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint64_t x = __builtin_bit_cast(uint64_t, hv[8 * h + 2 * q]), y = __builtin_bit_cast(uint64_t, hv[8 * h + 2 * q + 1]);
+      lds_st4(hs + h * SLAB + quad_off(lane, q), u4{(uint32_t)x, (uint32_t)(x >> 32), (uint32_t)y, (uint32_t)(y >> 32)});
+    }
+  (void)NC;
+}
+
+template <int RULE>
+__device__ __forceinline__ void compute_band64(const GridDesc& g, int band, WaveLds64* lds, WaveRings64* rings, int lane,
+                                               const KArgs& a) {
+  WaveLds64& L = lds[0];
+  const int64_t m = g.m, n = g.n, row0 = (int64_t)band * 64;
+  if (row0 >= m) return;
+  __builtin_amdgcn_s_setprio(3);
+  const int G = (int)groups_for(n, 1);
+  const int NC = (4 * G + CHUNK - 1) / CHUNK;
+  double H = absent64<RULE>();
+  if (g.left && row0 + lane < m) H = GC<double>(g.left)[row0 + lane];
+  // First T positions: 62 (column -1, the corner: NW of step 0) and 63 (column 0).
+  u4 q62 = lds_ld4_fresh(L8(&L.tring[62])), q63 = lds_ld4_fresh(L8(&L.tring[63]));
+  {
+    uint64_t t0 = 0;
+    uint32_t spins = 0;
+    while (__builtin_amdgcn_readfirstlane(probe_pos(q62) == SENT_F32 || probe_pos(q63) == SENT_F32 ? 1 : 0)) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 2047u) == 0u && (t0 = spin_check(lds, a.ctl, a.watchdog_ticks, t0)) == 0) break;
+      q62 = lds_ld4_fresh(L8(&L.tring[62]));
+      q63 = lds_ld4_fresh(L8(&L.tring[63]));
+    }
+  }
+  double Np = dec64(q62), tprev = dec64(q63);
+  CBAR();
+  if (lane < 4) lds_st4(L8(&L.tring[60 + lane]), u4{SENT_F32, SENT_F32, SENT_F32, SENT_F32});
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  const lds_u8* cs = L8(rings->cring);
+  lds_u8* hs = L8(rings->hring);
+  int k = 0;
+  for (; k < 4; ++k) compute_chunk64<RULE, 0>(k, NC, L, lds, cs, hs, lane, H, Np, tprev, a);
+  for (; k < NC; ++k) compute_chunk64<RULE, 1>(k, NC, L, lds, cs, hs, lane, H, Np, tprev, a);
+  CBAR();
+  if (lane == 0) {
+    st_ctl(&L.progress, (uint32_t)(4 * G));
+    st_ctl(&L.t_reset, (uint32_t)t_pad_end(G, 1));
+  }
+}
+
+// Loader: chunk k of the strip into c-ring slot k % C_SLOTS with LDS-DMA loads; load
+// (h, i) covers lane rows 16i .. 16i+15 of slab h, lane L reading row r = 16i + L/4 at
+// positions 16k + 8h + 2q, +1 with q = io_quad(L): columns col, col+1, col = that - r.
+__device__ __forceinline__ void loader_band64(const GridDesc& g, int band, WaveLds64* lds, WaveRings64* rings, int lane,
+                                              const KArgs& a) {
+  const int64_t m = g.m, n = g.n, row0 = (int64_t)band * 64;
+  if (row0 >= m) return;
+  WaveLds64& L = lds[0];
+  const int G = (int)groups_for(n, 1);
+  const int NC = (4 * G + CHUNK - 1) / CHUNK;
+  const int64_t span = (m - 1 - row0) * g.ld_cost + n;  // elements from the strip's first row to the grid's end
+  const uint32_t span_bytes = (uint32_t)(span * 8 < 0xFFFFFFF0ll ? span * 8 : 0xFFFFFFF0ll);
+  const __amdgpu_buffer_rsrc_t rsrc = make_rsrc((const double*)g.cost + row0 * g.ld_cost, span_bytes);
+  const int64_t last_r = m - 1 - row0;
+  const int lq = io_quad(lane);
+  int64_t rel[2][4];
+  int rr[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    rr[i] = 16 * i + (lane >> 2);
+    const int64_t rc = rr[i] < last_r ? rr[i] : last_r;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) rel[h][i] = rc * g.ld_cost + 8 * h + 2 * lq - rr[i];
+  }
+  int k_clean = 0;
+  if (row0 + 63 <= m - 1) {
+    const int64_t max_rel = 63 * g.ld_cost + 14 - 63;
+    const int64_t room = span - 2 - max_rel;
+    if (room >= 0) k_clean = (int)(room / 16 + 1 < NC ? room / 16 + 1 : NC);
+  }
+  const bool padded = g.ld_cost > n;
+  if (padded) {
+    const int k_pad = n >= 16 ? (int)((n - 16) / 16 + 1) : 0;
+    if (k_clean > k_pad) k_clean = k_pad;
+  }
+  const uint32_t slot0 = (uint32_t)(uintptr_t)L8(rings->cring);
+  int issued = 0, committed = 0;
+  Watch t_idle;
+  uint32_t polls = 0;
+  for (;;) {
+    while (issued < NC && (int)ld_ctl(&L.progress) >= 16 * (issued - C_SLOTS + 1)) {
+      const uint32_t base = __builtin_amdgcn_readfirstlane(slot0 + (uint32_t)((issued % C_SLOTS) * (2 * SLAB)));
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t e = rel[h][i] + 16 * issued;
+          const uint32_t voff = (issued < k_clean) ? (uint32_t)(e * 8)
+                                                   : ((e < 0 || e + 2 > span) ? 0xFFFFFFFFu : (uint32_t)(e * 8));
+          dma_quad16(rsrc, voff, base + (uint32_t)(SLAB * h + 1024 * i));
+        }
+      ++issued;
+    }
+    if (committed < issued) {
+      const int k = committed;
+      wait_dma<2>(issued - committed - 1);
+      if (k >= k_clean) {
+        // Quads that straddle the end of the grid or reach into row padding: element loads
+        // for the columns of the row, zeros past it.
+        bool fix[2][4];
+        bool any = false;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int64_t col = 16 * k + 8 * h + 2 * lq - rr[i];
+            const int64_t e = rel[h][i] + 16 * k;
+            fix[h][i] = rr[i] <= last_r && col + 1 >= 0 && ((e + 2 > span && col <= n - 1) || (padded && col + 1 > n - 1));
+            any |= fix[h][i];
+          }
+        if (__builtin_amdgcn_ballot_w64(any)) {
+          typedef __attribute__((address_space(1))) const uint64_t g64;
+          const g64* cb = (const g64*)(const void*)((const double*)g.cost + row0 * g.ld_cost);
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              if (!fix[h][i]) continue;
+              const int64_t col = 16 * k + 8 * h + 2 * lq - rr[i];
+              const uint64_t x = (col >= 0 && col <= n - 1) ? cb[(int64_t)rr[i] * g.ld_cost + col] : 0ull;
+              const uint64_t y = (col + 1 >= 0 && col + 1 <= n - 1) ? cb[(int64_t)rr[i] * g.ld_cost + col + 1] : 0ull;
+              lds_st4(L8(rings->cring) + (k % C_SLOTS) * (2 * SLAB) + SLAB * h + 1024 * i + 16 * lane,
+                      u4{(uint32_t)x, (uint32_t)(x >> 32), (uint32_t)y, (uint32_t)(y >> 32)});
+            }
+          __builtin_amdgcn_s_waitcnt(0xc07f);
+        }
+      }
+      CBAR();
+      if (lane == 0) st_ctl(&L.c_ready, (uint32_t)(k + 1));
+      ++committed;
+      t_idle.reset();
+      continue;
+    }
+    if (committed == NC) break;
+    bool ok = true;
+    while ((int)ld_ctl(&L.progress) < 16 * (issued - C_SLOTS + 1))
+      if (!(ok = io_idle<false>(lds, a, t_idle, polls))) break;
+    if (!ok) break;
+  }
+  wait_dma<2>(0);
+}
+
+// Storer: chunk k of H from the H ring to memory (full mode) or to the edge outputs, the
+// bottom row's positions of the chunk to the handoff row (encoded), then the slot is
+// released; the storer also re-arms the band above's handoff positions behind the feeder.
+__device__ __forceinline__ void storer_band64(const GridDesc& g, int band, WaveLds64* lds, WaveRings64* rings, int lane,
+                                              const KArgs& a) {
+  const int64_t m = g.m, n = g.n, row0 = (int64_t)band * 64;
+  if (row0 >= m) return;
+  WaveLds64& L = lds[0];
+  const int G = (int)groups_for(n, 1);
+  const int NC = (4 * G + CHUNK - 1) / CHUNK, T_END = 4 * G;
+  const int lq = io_quad(lane);
+  const bool full = g.mode == 0;
+  const bool handoff = band + 1 < g.nbands && a.fault_band != (uint32_t)band + 1u;
+  const __amdgpu_buffer_rsrc_t hand_out = make_rsrc(g.hand + (int64_t)band * g.hand_ld * 4, (uint32_t)(g.hand_ld * 16));
+  const __amdgpu_buffer_rsrc_t hand_in =
+      make_rsrc(g.hand + (band > 0 ? (int64_t)(band - 1) * g.hand_ld * 4 : 0), (uint32_t)(g.hand_ld * 16));
+  int ks = 0, hr = 60;
+  Watch t_idle;
+  uint32_t polls = 0;
+  for (;;) {
+    bool did = false;
+    const int prog = (int)ld_ctl(&L.progress);
+    CBAR();
+    while (ks < NC && prog >= (16 * (ks + 1) < T_END ? 16 * (ks + 1) : T_END)) {
+      const int k = ks;
+      const lds_u8* hs = L8(rings->hring) + (k % H64_SLOTS) * (2 * SLAB);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const u4 v = lds_ld4(hs + SLAB * h + 1024 * i + 16 * lane);
+          const int r = 16 * i + (lane >> 2);
+          const int64_t row = row0 + r;
+          const int64_t col = 16 * k + 8 * h + 2 * lq - r;
+          if (row >= m || col > n - 1 || col + 1 < 0) continue;
+          const uint64_t x[2] = {((uint64_t)v.y << 32) | v.x, ((uint64_t)v.w << 32) | v.z};
+          typedef __attribute__((address_space(1))) uint64_t g64;
+          if (full) {
+            g64* op = (g64*)(void*)((double*)g.out + row * g.ld_out);
+            if (col >= 0 && col + 1 <= n - 1) {
+              *(glb_u4a4*)(op + col) = v;
+            } else {
+#pragma unroll
+              for (int e = 0; e < 2; ++e)
+                if (col + e >= 0 && col + e <= n - 1) op[col + e] = x[e];
+            }
+          }
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            if (col + e < 0 || col + e > n - 1) continue;
+            if (col + e == n - 1 && g.last_col) ((g64*)(void*)g.last_col)[row] = x[e];
+            if (row == m - 1) {
+              if (g.last_row) ((g64*)(void*)g.last_row)[col + e] = x[e];
+              if (col + e == n - 1 && g.final_cell) *(g64*)(void*)g.final_cell = x[e];
+            }
+          }
+        }
+      if (handoff) {
+        // Positions 16k .. 16k + 15 of the bottom row (lane 63's row), the ones in [60, T_END).
+        const int p = 16 * k + (lane & 15);
+        if (lane < 16 && p >= 60 && p < T_END) {
+          const uint64_t x = *(const __attribute__((address_space(3))) uint64_t*)(hs + pos_off64(63, lane));
+          __builtin_amdgcn_raw_buffer_store_b128(enc64(__builtin_bit_cast(double, x)), hand_out, p * 16, 0, CPOL_SC1);
+        }
+      }
+      ++ks;
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // the ring reads are done before the slot is released
+      CBAR();
+      if (lane == 0) st_ctl(&L.h_done, (uint32_t)(16 * ks));
+      did = true;
+    }
+    if (band > 0) {
+      int fed = (int)ld_ctl(&L.t_fed);
+      if (fed > T_END) fed = T_END;
+      if (fed > hr) {
+        for (int p = hr + lane; p < fed; p += 64)
+          __builtin_amdgcn_raw_buffer_store_b128(u4{SENT_F32, SENT_F32, SENT_F32, SENT_F32}, hand_in, p * 16, 0, CPOL_SC1);
+        hr = fed;
+        did = true;
+      }
+    }
+    if (ks >= NC && (band == 0 || hr >= T_END)) break;
+    if (did) {
+      t_idle.reset();
+      continue;
+    }
+    if (!io_idle<false>(lds, a, t_idle, polls)) return;
+  }
+}
+
+// Feeder: T positions 60 .. T_END of the walk from the top boundary (band 0) or the
+// band above's handoff row, then absent values up to t_pad_end(G, 1).
+template <int RULE>
+__device__ __forceinline__ void feeder_band64(const GridDesc& g, int band, WaveLds64* lds, int lane, const KArgs& a) {
+  const int64_t m = g.m, n = g.n, row0 = (int64_t)band * 64;
+  if (row0 >= m) return;
+  WaveLds64& L = lds[0];
+  const int G = (int)groups_for(n, 1);
+  const int T_END = 4 * G, t_pad = t_pad_end(G, 1);
+  const __amdgpu_buffer_rsrc_t hand_in =
+      make_rsrc(g.hand + (band > 0 ? (int64_t)(band - 1) * g.hand_ld * 4 : 0), (uint32_t)(g.hand_ld * 16));
+  int tw = 60;
+  Watch t_idle;
+  uint32_t polls = 0;
+  while (tw < t_pad) {
+    int limit = (int)ld_ctl(&L.t_reset) + RT64;
+    if (limit > t_pad) limit = t_pad;
+    CBAR();
+    int got = 0;
+    if (tw < limit) {
+      const int nq = limit - tw < 64 ? limit - tw : 64;
+      const int p = tw + lane;
+      u4 v = u4{SENT_F32, SENT_F32, SENT_F32, SENT_F32};
+      bool valid = false;
+      if (lane < nq) {
+        if (band == 0 || p >= T_END) {
+          double val = absent64<RULE>();
+          const int64_t ti = (int64_t)p - 62;  // index into top[] (= column + 1)
+          if (band == 0 && ti >= 0 && ti <= n) {
+            if (g.top) val = GC<double>(g.top)[ti];
+            else if (ti == 0) val = 0.0;
+          }
+          v = enc64(val);
+          valid = true;
+        } else {
+          v = __builtin_amdgcn_raw_buffer_load_b128(hand_in, p * 16, 0, CPOL_SC1);
+          valid = probe_pos(v) != SENT_F32;
+        }
+      }
+      const uint64_t bal = __builtin_amdgcn_ballot_w64(valid);
+      got = ~bal == 0ull ? 64 : (int)__builtin_ctzll(~bal);
+      if (got > nq) got = nq;
+      if (lane < got) lds_st4(L8(&L.tring[p & (RT64 - 1)]), v);
+      if (got) {
+        tw += got;
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        CBAR();
+        if (lane == 0) st_ctl(&L.t_fed, (uint32_t)tw);
+      }
+    }
+    if (got) {
+      t_idle.reset();
+      continue;
+    }
+    if (!io_idle<true>(lds, a, t_idle, polls)) break;
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// Waves: 0 compute, 1 loader, 2 storer, 3 feeder (one per SIMD).
+template <int RULE>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
+void wf_sweep64_kernel(KArgs a) {
+  __shared__ WaveLds64 lds[1];
+  __shared__ WaveRings64 rings;
+  __shared__ uint32_t s_item;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      uint32_t t = atomicAdd(&a.ctl[CTL_TICKET], 1u);
+      if (ld_dev(a.ctl + CTL_ABORT)) t = 0xFFFFFFFFu;
+      s_item = t;
+    }
+    if (wave == 0) {
+      WaveLds64& L = lds[0];
+      for (int i = lane; i < RT64; i += 64) L.tring[i] = u4{SENT_F32, SENT_F32, SENT_F32, SENT_F32};
+      if (lane == 0) {
+        L.c_ready = 0;
+        L.h_done = 0;
+        L.progress = (uint32_t)-16;
+        L.t_reset = 60;
+        L.t_fed = 60;
+        L.abort = 0;
+      }
+    }
+    __syncthreads();
+    const uint32_t t = __builtin_amdgcn_readfirstlane(s_item);
+    if ((int64_t)t >= a.nitems) break;
+    GridDesc gd;
+    int band;
+    if (a.grids) {
+      const Item it = a.items[t];
+      gd = a.grids[it.grid];
+      band = (int)it.band;
+    } else {
+      gd = a.g0;
+      band = (int)t;
+    }
+    if (wave == 0) compute_band64<RULE>(gd, band, lds, &rings, lane, a);
+    else if (wave == 1) loader_band64(gd, band, lds, &rings, lane, a);
+    else if (wave == 2) storer_band64(gd, band, lds, &rings, lane, a);
+    else feeder_band64<RULE>(gd, band, lds, lane, a);
+    __syncthreads();
+  }
+}
+
+// Traceback of a computed grid: from (m-1, n-1), step to the predecessor whose value the
+// rule selects, NW before N before W on equal values, until that predecessor lies
+// outside the grid.  One wave.  It stages in LDS the 64 x 64 block of values whose
+// bottom-right cell is the walk's current cell -- 63 x 63 cells of H and the row above
+// and the column left of them (from H, or the boundary) -- and every lane turns one
+// column of it into predecessor codes; lane 0 then follows the codes until the walk
+// leaves the block, and the wave stages the next one.
+constexpr int TB = 64;  // staged block side (63 cells + one boundary row / column)
+
+template <typename T, int RULE>
+__global__ void __launch_bounds__(64) traceback_kernel(const T* H, int64_t ld, int64_t m, int64_t n, const T* top,
+                                                       const T* left, int32_t* path, int64_t* length) {
+  __shared__ T blk[TB][TB];            // blk[a][b]: row i0 - 1 + a, column j0 - 1 + b
+  __shared__ uint8_t code[TB][TB];     // 0: NW, 1: N, 2: W
+  __shared__ int64_t s_state[3];
+  const int lane = threadIdx.x;
+  const T absent = Num<T>::template absent<RULE>();
+  int64_t i = m - 1, j = n - 1, k = 0;
+  for (;;) {
+    const int64_t i0 = i - (TB - 2) > 0 ? i - (TB - 2) : 0;
+    const int64_t j0 = j - (TB - 2) > 0 ? j - (TB - 2) : 0;
+    // Lane b stages column j0 - 1 + b of rows i0 - 1 .. i0 + 62 (all loads in flight at once).
+    const int64_t col = j0 - 1 + lane;
+    T v[TB];
+#pragma unroll
+    for (int a = 0; a < TB; ++a) {
+      const int64_t r = i0 - 1 + a;
+      T x = absent;
+      if (r <= i && col <= j) {
+        if (r < 0) x = top ? top[col + 1] : (col == -1 ? (T)0 : absent);
+        else if (col < 0) x = left ? left[r] : absent;
+        else x = H[r * ld + col];
+      }
+      v[a] = x;
+    }
+#pragma unroll
+    for (int a = 0; a < TB; ++a) blk[a][lane] = v[a];
+    __syncthreads();
+    if (lane >= 1) {
+#pragma unroll 4
+      for (int a = 1; a < TB; ++a) {
+        const T nw = blk[a - 1][lane - 1], nn = blk[a - 1][lane], ww = blk[a][lane - 1];
+        T best = nw;
+        uint8_t c = 0;
+        if (RULE == 0 ? nn < best : nn > best) { best = nn; c = 1; }
+        if (RULE == 0 ? ww < best : ww > best) c = 2;
+        code[a][lane] = c;
+      }
+    }
+    __syncthreads();
+    if (lane == 0) {
+      int64_t ci = i, cj = j;
+      while (ci >= i0 && cj >= j0) {
+        path[2 * k] = (int32_t)ci;
+        path[2 * k + 1] = (int32_t)cj;
+        ++k;
+        const uint8_t c = code[ci - i0 + 1][cj - j0 + 1];
+        ci -= c == 2 ? 0 : 1;
+        cj -= c == 1 ? 0 : 1;
+      }
+      s_state[0] = ci;
+      s_state[1] = cj;
+      s_state[2] = k;
+    }
+    __syncthreads();
+    i = s_state[0];
+    j = s_state[1];
+    k = s_state[2];
+    __syncthreads();
+    if (i < 0 || j < 0) break;
+  }
+  if (lane == 0) {
+    path[2 * k] = (int32_t)i;
+    path[2 * k + 1] = (int32_t)j;
+    *length = k;
+  }
+}
+
 // Set-up of an allocation-free launch: zero the control words (the error word only when
 // asked: it accumulates across launches until the host has seen it) and arm `count`
 // handoff-row words with the sentinel.
@@ -1333,6 +1966,12 @@ size_t lds_bytes(int W, int R) {
 }
 
 hipError_t launch_sweep(int dtype, int rule, int W, int R, int nwg, const KArgs& args, hipStream_t stream) {
+  if (dtype == 2) {
+    if (W != 1 || R != 1) return hipErrorInvalidValue;
+    if (rule == 0) hipLaunchKernelGGL((wf_sweep64_kernel<0>), dim3(nwg), dim3(256), 0, stream, args);
+    else hipLaunchKernelGGL((wf_sweep64_kernel<1>), dim3(nwg), dim3(256), 0, stream, args);
+    return hipGetLastError();
+  }
   if (dtype == 0)
     return rule == 0 ? launch_w<float, 0>(W, R, nwg, args, stream) : launch_w<float, 1>(W, R, nwg, args, stream);
   if (dtype == 1)
@@ -1347,6 +1986,27 @@ hipError_t launch_noalloc_prep(uint32_t* ctl, bool reset_error, uint32_t* hand, 
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(noalloc_prep_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, ctl,
                      reset_error ? 1u : 0u, hand, sent, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_traceback(int dtype, int rule, const void* H, int64_t ld, int64_t m, int64_t n, const void* top,
+                            const void* left, int32_t* path, int64_t* length, hipStream_t stream) {
+#define WF_TB(T, RL)                                                                                           \
+  hipLaunchKernelGGL((traceback_kernel<T, RL>), dim3(1), dim3(64), 0, stream, (const T*)H, ld, m, n, (const T*)top, \
+                     (const T*)left, path, length)
+  if (dtype == 0) {
+    if (rule == 0) WF_TB(float, 0);
+    else WF_TB(float, 1);
+  } else if (dtype == 1) {
+    if (rule == 0) WF_TB(int32_t, 0);
+    else WF_TB(int32_t, 1);
+  } else if (dtype == 2) {
+    if (rule == 0) WF_TB(double, 0);
+    else WF_TB(double, 1);
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef WF_TB
   return hipGetLastError();
 }
 

@@ -186,14 +186,24 @@ wf_status wfh::check_problem(const wf_problem* p, int64_t idx) {
   if (!p) return fail(WF_EINVAL, std::string(where) + "NULL problem");
   if (p->m < 0 || p->n < 0) return fail(WF_EINVAL, std::string(where) + "m and n must be >= 0");
   if (p->n > MAX_N) return fail(WF_EUNSUPPORTED, std::string(where) + "n above 2^23 is not supported");
-  if (p->dtype != WF_F32 && p->dtype != WF_I32) return fail(WF_EINVAL, std::string(where) + "unknown dtype");
+  if (p->dtype != WF_F32 && p->dtype != WF_I32 && p->dtype != WF_F64)
+    return fail(WF_EINVAL, std::string(where) + "unknown dtype");
+  if (p->dtype == WF_F64 && (p->n > MAX_N / 2 || p->ld_cost > MAX_N / 2 || p->ld_out > MAX_N / 2))
+    return fail(WF_EUNSUPPORTED, std::string(where) + "fp64 grids need n and leading dimensions <= 2^22");
   if (p->rule != WF_RULE_MIN && p->rule != WF_RULE_MAX) return fail(WF_EINVAL, std::string(where) + "unknown rule");
   if (p->mode != WF_MODE_FULL && p->mode != WF_MODE_EDGES) return fail(WF_EINVAL, std::string(where) + "unknown mode");
-  if (p->flags != 0) return fail(WF_EINVAL, std::string(where) + "flags must be 0");
+  if (p->flags != 0 && p->flags != WF_COST_ABSDIFF)
+    return fail(WF_EINVAL, std::string(where) + "flags must be 0 or WF_COST_ABSDIFF");
+  if (p->flags == WF_COST_ABSDIFF && p->dtype != WF_F32)
+    return fail(WF_EUNSUPPORTED, std::string(where) + "WF_COST_ABSDIFF needs WF_F32");
   if (p->m == 0 || p->n == 0) return WF_OK;
-  if (!p->cost) return fail(WF_EINVAL, std::string(where) + "cost is NULL");
-  if (p->ld_cost < p->n) return fail(WF_EINVAL, std::string(where) + "ld_cost < n");
-  if (p->ld_cost > MAX_N) return fail(WF_EUNSUPPORTED, std::string(where) + "ld_cost above 2^23 is not supported");
+  if (p->flags == WF_COST_ABSDIFF) {
+    if (!p->seq_x || !p->seq_y) return fail(WF_EINVAL, std::string(where) + "seq_x or seq_y is NULL");
+  } else {
+    if (!p->cost) return fail(WF_EINVAL, std::string(where) + "cost is NULL");
+    if (p->ld_cost < p->n) return fail(WF_EINVAL, std::string(where) + "ld_cost < n");
+    if (p->ld_cost > MAX_N) return fail(WF_EUNSUPPORTED, std::string(where) + "ld_cost above 2^23 is not supported");
+  }
   if (p->mode == WF_MODE_FULL) {
     if (!p->out) return fail(WF_EINVAL, std::string(where) + "out is NULL in FULL mode");
     if (p->ld_out < p->n) return fail(WF_EINVAL, std::string(where) + "ld_out < n");
@@ -228,7 +238,7 @@ int wfh::choose_shape(int64_t m) {
 
 // The LDS rings of one compute wave of one row per lane take about 66 KB of a compute
 // unit's 160 KB, so two such workgroups fit; the other shapes take twice that.
-int wfh::wgs_per_cu(int bs) { return bs == 1 ? 2 : 1; }
+int wfh::wgs_per_cu(int bs, int dtype) { return bs == 1 && dtype != WF_F64 ? 2 : 1; }
 
 hipError_t wfh::launch_shape(int dtype, int rule, int bs, int nwg, const KArgs& args, hipStream_t stream) {
   return launch_sweep(dtype, rule, shape_waves(bs), shape_rows_per_lane(bs), nwg, args, stream);
@@ -242,12 +252,16 @@ static int shape_of_tuning(const wf_tuning& t, int64_t m) {
   return 1;
 }
 
-uint32_t wfh::sentinel_of(int dtype) { return dtype == WF_F32 ? SENT_F32 : SENT_I32; }
+uint32_t wfh::sentinel_of(int dtype) { return dtype == WF_I32 ? SENT_I32 : SENT_F32; }
 
 GridDesc wfh::make_desc(const wf_problem* p, int bs, uint32_t* hand) {
   GridDesc d;
   std::memset(&d, 0, sizeof d);
-  d.cost = p->cost;
+  const bool absdiff = p->flags == WF_COST_ABSDIFF;
+  d.cost = absdiff ? nullptr : p->cost;
+  d.sx = absdiff ? p->seq_x : nullptr;
+  d.sy = absdiff ? p->seq_y : nullptr;
+  d.kind = absdiff ? 1 : 0;
   d.out = p->mode == WF_MODE_FULL ? p->out : nullptr;
   d.top = p->top;
   d.left = p->left;
@@ -257,7 +271,7 @@ GridDesc wfh::make_desc(const wf_problem* p, int bs, uint32_t* hand) {
   d.hand = hand;
   d.m = p->m;
   d.n = p->n;
-  d.ld_cost = p->ld_cost;
+  d.ld_cost = absdiff ? p->n : p->ld_cost;
   d.ld_out = p->mode == WF_MODE_FULL ? p->ld_out : 0;
   d.hand_ld = hand_ld_for(p->n, shape_rows_per_lane(bs));
   d.mode = p->mode;
@@ -267,7 +281,9 @@ GridDesc wfh::make_desc(const wf_problem* p, int bs, uint32_t* hand) {
 
 size_t wfh::hand_elems(const wf_problem* p, int bs) {
   const int64_t nb = (p->m + shape_rows(bs) - 1) / shape_rows(bs);
-  return nb > 1 ? (size_t)(nb - 1) * (size_t)hand_ld_for(p->n, shape_rows_per_lane(bs)) : 0;
+  // fp64 positions travel encoded in four words
+  const size_t words = p->dtype == WF_F64 ? 4 : 1;
+  return nb > 1 ? (size_t)(nb - 1) * (size_t)hand_ld_for(p->n, shape_rows_per_lane(bs)) * words : 0;
 }
 
 KArgs wfh::base_args(wf_ctx* ctx, uint32_t* ctl, int64_t nitems) {
@@ -490,7 +506,7 @@ static wf_status solve_one(wf_ctx* ctx, const wf_problem* p, int bs, int max_wgs
   KArgs a = base_args(ctx, s->ctl, 0);
   a.g0 = make_desc(p, bs, s->hand);
   a.nitems = a.g0.nbands;
-  const int resident = ctx->num_cus * wgs_per_cu(bs);
+  const int resident = ctx->num_cus * wgs_per_cu(bs, p->dtype);
   int nwg = (int)std::min<int64_t>(a.nitems, resident);
   if (max_wgs > 0) nwg = std::min(nwg, max_wgs);
   // Optional trace (profiling hook): WF_TRACE_FILE=<path> makes wf_solve synchronous
@@ -551,6 +567,7 @@ static wf_status solve_entry(wf_ctx* ctx, const wf_problem* p, const wf_tuning* 
   if (st != WF_OK) return st;
   if (p->m == 0 || p->n == 0) return WF_OK;
   const int bs = shape_of_tuning(tun, p->m);
+  if (p->dtype == WF_F64 && bs != 1) return fail(WF_EUNSUPPORTED, "fp64 grids use 64-row bands only");
   return solve_one(ctx, p, bs, tun.max_wgs, (hipStream_t)stream_);
 }
 
@@ -590,11 +607,28 @@ extern "C" wf_status wf_solve_noalloc(wf_ctx* ctx, const wf_problem* p, void* st
   KArgs a = base_args(ctx, s.ctl, 0);
   a.g0 = make_desc(p, bs, s.hand);
   a.nitems = a.g0.nbands;
-  const int nwg = (int)std::min<int64_t>(a.nitems, (int64_t)ctx->num_cus * wgs_per_cu(bs));
+  const int nwg = (int)std::min<int64_t>(a.nitems, (int64_t)ctx->num_cus * wgs_per_cu(bs, p->dtype));
   WF_HIP(launch_noalloc_prep(s.ctl, s.needs_rearm, s.hand, sentinel_of(p->dtype), (int64_t)need, stream));
   s.needs_rearm = false;
   WF_HIP(launch_shape(p->dtype, p->rule, bs, nwg, a, stream));
   return finish_launch(s, stream);
+}
+
+extern "C" wf_status wf_traceback(wf_ctx* ctx, const wf_problem* p, int32_t* path, int64_t* length, void* stream) {
+  if (!ctx) return fail(WF_EINVAL, "ctx is NULL");
+  if (!p || !path || !length) return fail(WF_EINVAL, "NULL problem, path or length");
+  if (p->m < 1 || p->n < 1) return fail(WF_EINVAL, "traceback needs m, n >= 1");
+  if (p->dtype != WF_F32 && p->dtype != WF_I32 && p->dtype != WF_F64) return fail(WF_EINVAL, "unknown dtype");
+  if (p->rule != WF_RULE_MIN && p->rule != WF_RULE_MAX) return fail(WF_EINVAL, "unknown rule");
+  if (!p->out) return fail(WF_EINVAL, "out (the computed grid) is NULL");
+  if (p->ld_out < p->n) return fail(WF_EINVAL, "ld_out < n");
+  wf_status st = set_device(ctx);
+  if (st != WF_OK) return st;
+  st = report_sticky(ctx);
+  if (st != WF_OK) return st;
+  WF_HIP(launch_traceback(p->dtype, p->rule, p->out, p->ld_out, p->m, p->n, p->top, p->left, path,
+                          length, (hipStream_t)stream));
+  return WF_OK;
 }
 
 extern "C" wf_status wf_solve_tuned(wf_ctx* ctx, const wf_problem* p, const wf_tuning* t, void* stream) {
@@ -662,8 +696,8 @@ static void build_work(const wf_problem* ps, int64_t count, int bs, int order, s
   }
 }
 
-static int batch_wgs(const wf_ctx* ctx, int bs, int64_t nitems, int max_wgs) {
-  int nwg = (int)std::min<int64_t>(nitems, (int64_t)ctx->num_cus * wgs_per_cu(bs));
+static int batch_wgs(const wf_ctx* ctx, int bs, int dtype, int64_t nitems, int max_wgs) {
+  int nwg = (int)std::min<int64_t>(nitems, (int64_t)ctx->num_cus * wgs_per_cu(bs, dtype));
   if (max_wgs > 0) nwg = std::min(nwg, max_wgs);
   return std::max(nwg, 1);
 }
@@ -693,7 +727,7 @@ static wf_status batched_once(wf_ctx* ctx, const wf_problem* ps, int64_t count, 
   a.grids = s->grids;
   a.items = s->items;
   WF_HIP(launch_fill_u32(s->ctl, 0u, CTL_WORDS, stream));
-  WF_HIP(launch_shape(ps[perm[0]].dtype, ps[perm[0]].rule, bs, batch_wgs(ctx, bs, a.nitems, max_wgs), a, stream));
+  WF_HIP(launch_shape(ps[perm[0]].dtype, ps[perm[0]].rule, bs, batch_wgs(ctx, bs, ps[perm[0]].dtype, a.nitems, max_wgs), a, stream));
   return finish_launch(*s, stream);
 }
 
@@ -752,7 +786,7 @@ static wf_status batched_plan(wf_ctx* ctx, const wf_problem* ps, int64_t count, 
       n->rule = rule;
       n->use_graph = use_graph;
       build_work(ps, count, bs, order, n->perm, n->items, n->hand_off, n->hand_total);
-      n->nwg = batch_wgs(ctx, bs, (int64_t)n->items.size(), max_wgs);
+      n->nwg = batch_wgs(ctx, bs, dtype, (int64_t)n->items.size(), max_wgs);
       ctx->plans.push_back(std::move(n));
       e = ctx->plans.back().get();
     }
@@ -854,8 +888,10 @@ static wf_status autotune(wf_ctx* ctx, const wf_problem* ps, int64_t count, int 
   TuneEntry best;
   best.ms = -1;
   wf_status st = WF_OK;
-  for (int bs = 1; bs <= SHAPE_MAX && st == WF_OK; ++bs) {
-    const int resident = ctx->num_cus * wgs_per_cu(bs);
+  // fp64 grids have one band shape only.
+  const int max_shape = ps[0].dtype == WF_F64 ? 1 : SHAPE_MAX;
+  for (int bs = 1; bs <= max_shape && st == WF_OK; ++bs) {
+    const int resident = ctx->num_cus * wgs_per_cu(bs, ps[0].dtype);
     const int wg_opts[2] = {max_wgs > 0 ? std::min(max_wgs, resident) : resident,
                             std::max(1, (max_wgs > 0 ? std::min(max_wgs, resident) : resident) / 2)};
     for (int order = 1; order <= 2 && st == WF_OK; ++order) {
@@ -926,6 +962,7 @@ extern "C" wf_status wf_solve_batched(wf_ctx* ctx, const wf_problem* ps, int64_t
     wgs = te.wgs;
   }
   if (bs == 0) bs = 1;
+  if (ps[0].dtype == WF_F64 && bs != 1) return fail(WF_EUNSUPPORTED, "fp64 grids use 64-row bands only");
   if (order == 0) order = 1;
   if (tun.use_graph == 1) return batched_plan(ctx, ps, count, bs, order, wgs, true, stream);
   return batched_once(ctx, ps, count, bs, order, wgs, stream);

@@ -405,12 +405,12 @@ void wf_server::admit(double t) {
 
 wf_status wf_server::enqueue(LaunchSlot& L, std::vector<Req*>& batch, int bs, int dtype, int rule) {
   hipStream_t s = L.stream;
-  // Host inputs without copy streams go through the slot's pinned staging buffer on the
+  // Pageable host inputs without copy streams go through the slot's pinned staging buffer on the
   // launch stream: a copy from pageable memory is staged synchronously by the runtime in
   // the calling thread, which would make the server thread block on the device.
   size_t stage = 0;
   for (Req* q : batch)
-    if (host_input(q->r) && !q->copied) stage += (size_t)q->r.m * (size_t)q->r.n * 4;
+    if (q->r.input_kind == WF_INPUT_HOST && !q->copied) stage += (size_t)q->r.m * (size_t)q->r.n * 4;
   if (stage) {
     wf_status st = grow_host(&L.h_stage, &L.h_stage_cap, stage);
     if (st != WF_OK) return st;
@@ -420,6 +420,14 @@ wf_status wf_server::enqueue(LaunchSlot& L, std::vector<Req*>& batch, int bs, in
   for (Req* q : batch) {
     if (q->copied) {
       WF_HIP(hipStreamWaitEvent(s, q->copied, 0));
+    } else if (q->r.input_kind == WF_INPUT_HOST_PINNED) {
+      // Pinned memory is copied by DMA directly, on the launch stream.
+      const size_t row = (size_t)q->r.n * 4;
+      if (q->r.ld_input == q->r.n)
+        WF_HIP(hipMemcpyAsync((void*)q->in, q->r.input, row * (size_t)q->r.m, hipMemcpyHostToDevice, s));
+      else
+        WF_HIP(hipMemcpy2DAsync((void*)q->in, row, q->r.input, (size_t)q->r.ld_input * 4, row, (size_t)q->r.m,
+                                hipMemcpyHostToDevice, s));
     } else if (host_input(q->r)) {
       const size_t row = (size_t)q->r.n * 4, bytes = row * (size_t)q->r.m;
       for (int64_t i = 0; i < q->r.m; ++i)
@@ -468,7 +476,7 @@ wf_status wf_server::enqueue(LaunchSlot& L, std::vector<Req*>& batch, int bs, in
   KArgs a = base_args(ctx, L.ctl, (int64_t)nitems);
   a.grids = L.d_grids;
   a.items = L.d_items;
-  const int nwg = (int)std::min<int64_t>((int64_t)nitems, (int64_t)ctx->num_cus * wgs_per_cu(bs));
+  const int nwg = (int)std::min<int64_t>((int64_t)nitems, (int64_t)ctx->num_cus * wgs_per_cu(bs, dtype));
   WF_HIP(launch_fill_u32(L.ctl, 0u, CTL_WORDS, s));
   WF_HIP(launch_shape(dtype, rule, bs, nwg, a, s));
   WF_HIP(hipMemcpyAsync(L.host_err, L.ctl + CTL_ERROR, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -637,6 +645,7 @@ extern "C" wf_status wf_server_create(wf_ctx* ctx, const wf_server_opts* opts, w
 extern "C" wf_status wf_submit(wf_server* s, const wf_request* r, uint64_t* ticket) {
   if (!s || !r || !ticket) return fail(WF_EINVAL, "server, request and ticket must not be NULL");
   if (r->m < 0 || r->n < 0) return fail(WF_EINVAL, "m and n must be >= 0");
+  if (r->dtype == WF_F64) return fail(WF_EUNSUPPORTED, "the server serves fp32 and int32 grids");
   if (r->dtype != WF_F32 && r->dtype != WF_I32) return fail(WF_EINVAL, "unknown dtype");
   if (r->rule != WF_RULE_MIN && r->rule != WF_RULE_MAX) return fail(WF_EINVAL, "unknown rule");
   if (r->mode != WF_MODE_FULL && r->mode != WF_MODE_EDGES) return fail(WF_EINVAL, "unknown mode");

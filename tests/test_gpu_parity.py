@@ -46,7 +46,7 @@ def _gamma_bound(H64):
 
 
 def _case(m, n, rule="min", dtype="f32", seed=1, explicit=False, ld_pad=0, pad_value=0, waves_per_wg=0,
-          rows_per_lane=0):
+          rows_per_lane=0, sides="both"):
     print(f"[parity] m={m} n={n} rule={rule} dtype={dtype} seed={seed} explicit={explicit} ld_pad={ld_pad} "
           f"pad_value={pad_value} W={waves_per_wg} R={rows_per_lane}", flush=True)
     c = wfgen.cells(seed, m, n, dtype)
@@ -54,6 +54,10 @@ def _case(m, n, rule="min", dtype="f32", seed=1, explicit=False, ld_pad=0, pad_v
     if explicit:
         top = (wfgen.vector(seed + 100, n + 1, dtype) * (3 if dtype == "f32" else 2)).astype(c.dtype)
         left = (wfgen.vector(seed + 200, m, dtype) * (3 if dtype == "f32" else 2)).astype(c.dtype)
+        if sides == "top":
+            left = None
+        elif sides == "left":
+            top = None
     if ld_pad:
         cb = np.full((m, n + ld_pad), pad_value, np.uint32).view(c.dtype)
         cb[:, :n] = c
@@ -154,6 +158,17 @@ def test_two_rows_per_lane(m, n, dtype):
     row to several bands, with ragged last bands."""
     _case(m, n, dtype=dtype, seed=13, rows_per_lane=2)
     _case(m, n, rule="max", dtype=dtype, seed=14, explicit=True, rows_per_lane=2)
+
+
+@pytest.mark.parametrize("m,n", [(65, 65), (300, 513), (2100, 333)])
+@pytest.mark.parametrize("sides", ["top", "left"])
+@pytest.mark.parametrize("R", [1, 2])
+def test_one_sided_explicit_boundary(m, n, sides, R):
+    """An explicit top with the default left boundary takes the first chunks without
+    per-cell selection (the cells left of column 0 stay absent by themselves); an explicit
+    left boundary takes them with it.  Both bit-exact, both rules."""
+    _case(m, n, seed=15, explicit=True, sides=sides, rows_per_lane=R)
+    _case(m, n, rule="max", seed=16, explicit=True, sides=sides, rows_per_lane=R)
 
 
 def test_two_waves_of_two_rows_is_rejected():

@@ -276,3 +276,30 @@ def test_traceback_of_dtw_identical_sequences_is_the_diagonal():
     path, ex = oracle.traceback(oracle.dtw(x, x), "min")
     assert [tuple(p) for p in path] == [(i, i) for i in range(63, -1, -1)]
     assert tuple(ex) == (-1, -1)
+
+
+def _python_traceback(H, order):
+    """A copy of the traceback rule in Python with a given preference order, for the
+    planted-mistake check below."""
+    m, n = H.shape
+    i, j, path = m - 1, n - 1, []
+    moves = {"NW": (-1, -1), "N": (-1, 0), "W": (0, -1)}
+    while i >= 0 and j >= 0:
+        path.append((i, j))
+        vals = {}
+        for name, (di, dj) in moves.items():
+            a, b = i + di, j + dj
+            vals[name] = (0.0 if (a, b) == (-1, -1) else np.inf) if (a < 0 or b < 0) else float(H[a, b])
+        best = min(vals[o] for o in order)
+        pick = next(o for o in order if vals[o] == best)
+        i, j = i + moves[pick][0], j + moves[pick][1]
+    return path
+
+
+def test_planted_tiebreak_mistake_is_caught():
+    """Preferring N over NW (a plausible slip) changes the path on a constant grid, where
+    the closed-form pin above fixes the diagonal first; the oracle's own order passes it."""
+    H = oracle.sweep(np.ones((9, 4), np.float32), "min", "f32")
+    path, _ = oracle.traceback(H, "min")
+    assert _python_traceback(H, ("NW", "N", "W")) == [tuple(p) for p in path]
+    assert _python_traceback(H, ("N", "NW", "W")) != [tuple(p) for p in path]

@@ -14,6 +14,7 @@ seeded with `seed` is  mix64(seed + (k+1) * GAMMA)  with
 
 Mapping to cell values:
   float32: top 24 bits, (x >> 40) * 2^-24   -> uniform on [0, 1), exact in fp32
+  float64: top 53 bits, (x >> 11) * 2^-53   -> uniform on [0, 1), exact in fp64
   int32:   low 8 bits,  x & 255             -> uniform on {0, ..., 255}
 
 Workload recipes (sizes, seeds, arrival times) for the benchmark
@@ -46,6 +47,8 @@ def _to_dtype(x: np.ndarray, dtype: str) -> np.ndarray:
         return ((x >> np.uint64(40)).astype(np.float64) * (2.0 ** -24)).astype(np.float32)
     if dtype == "i32":
         return (x & np.uint64(255)).astype(np.int32)
+    if dtype == "f64":
+        return (x >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
     raise ValueError(f"unknown dtype {dtype!r}")
 
 
@@ -134,7 +137,7 @@ def fill_device(t, seed: int, row0: int = 0, n_cols: int | None = None, stream=N
         raise ValueError("a band must span the full grid width")
     if t.stride(1) != 1:
         raise ValueError("unit column stride required")
-    dt = {torch.float32: 0, torch.int32: 1}[t.dtype]
+    dt = {torch.float32: 0, torch.int32: 1, torch.float64: 2}[t.dtype]
     s = stream if stream is not None else torch.cuda.current_stream()
     rc = _fill_lib.wfgen_fill(t.data_ptr(), dt, rows, n, t.stride(0), seed & 0xFFFFFFFFFFFFFFFF, row0,
                               s.cuda_stream)

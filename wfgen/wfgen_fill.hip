@@ -1,7 +1,8 @@
 // Device-side fill with the SplitMix64 counter generator (Steele, Lea, Flood,
 // OOPSLA 2014): cell (i, j) of an n-column grid gets output k = i*n + j of the
 // stream seeded with `seed`, mapped exactly as wfgen/__init__.py maps it
-// (float32: (x >> 40) * 2^-24; int32: x & 255).  Input generation only.
+// (float32: (x >> 40) * 2^-24; float64: (x >> 11) * 2^-53; int32: x & 255).  Input
+// generation only.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -21,6 +22,7 @@ __global__ void fill_kernel(void* dst, int dtype, int64_t rows, int64_t n, int64
     const int64_t i = t / n, j = t - i * n;
     const uint64_t x = splitmix64_at(seed, (uint64_t)(row0 + i) * (uint64_t)n + (uint64_t)j);
     if (dtype == 0) ((float*)dst)[i * ld + j] = (float)(x >> 40) * 5.9604644775390625e-08f;  // 2^-24, exact
+    else if (dtype == 2) ((double*)dst)[i * ld + j] = (double)(x >> 11) * 1.1102230246251565e-16;  // 2^-53, exact
     else ((int32_t*)dst)[i * ld + j] = (int32_t)(x & 255u);
   }
 }
@@ -28,11 +30,11 @@ __global__ void fill_kernel(void* dst, int dtype, int64_t rows, int64_t n, int64
 }  // namespace
 
 // Fill rows [row0, row0 + rows) of an n-column grid into dst (row stride ld elements).
-// dtype: 0 = float32, 1 = int32.  Returns 0 or a hipError_t value.
+// dtype: 0 = float32, 1 = int32, 2 = float64.  Returns 0 or a hipError_t value.
 extern "C" int wfgen_fill(void* dst, int dtype, int64_t rows, int64_t n, int64_t ld, uint64_t seed, int64_t row0,
                           void* stream) {
   if (rows <= 0 || n <= 0) return 0;
-  if (!dst || ld < n || (dtype != 0 && dtype != 1)) return (int)hipErrorInvalidValue;
+  if (!dst || ld < n || dtype < 0 || dtype > 2) return (int)hipErrorInvalidValue;
   int64_t blocks = (rows * n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, dst, dtype, rows, n, ld,
