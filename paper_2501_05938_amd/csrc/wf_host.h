@@ -32,6 +32,7 @@ struct Slot {
   bool needs_rearm = false;       // an aborted launch left handoff rows written: refill before reuse
   bool reserved = false;          // held by a cached batch plan
   bool external = false;          // ctl/hand live in memory the slot does not own
+  bool xcd_queues = false;        // its last launch used XCD queues
 };
 
 // A batch whose work list, descriptor tables and (optionally) captured graphs are
@@ -79,6 +80,10 @@ struct wf_ctx {
   std::string tune_file;                   // WF_TUNE_CACHE: where `tuned` persists (empty: memory only)
   wf_status sticky = WF_OK;                // device error seen, reported once
   Slot* noalloc = nullptr;                 // wf_solve_noalloc's slot: ctl/hand in the fixed device array
+  // XCD queues of single-grid launches: the number of XCDs when the placement probe at
+  // wf_init found workgroup w of a launch on XCD w % nx, else 1 (off).  WF_XCD_QUEUES=0
+  // turns them off.
+  int nx = 1;
 };
 
 namespace wfh {
@@ -111,6 +116,9 @@ size_t hand_elems(const wf_problem* p, int bs);
 // Arguments of a launch over `nitems` work items with the context's watchdog and fault hook.
 // (Consumes the context's one-shot fault hook.)
 wfk::KArgs base_args(wf_ctx* ctx, uint32_t* ctl, int64_t nitems);
+// XCD queues for a single-grid launch of nwg workgroups (see KArgs::nx), when the context
+// has them and the launch has a workgroup for every XCD.
+void xcd_queues(const wf_ctx* ctx, wfk::KArgs& a, int nwg, int dtype);
 
 }  // namespace wfh
 

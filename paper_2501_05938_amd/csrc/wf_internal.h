@@ -43,6 +43,14 @@ struct KArgs {
   uint64_t* ctrace;       // optional: CTRACE_WORDS per (work item, compute wave, chunk), see below
   int64_t ctrace_nc;      // chunks per (work item, compute wave) in ctrace
   uint32_t fault_band;    // test hook: band (of every grid) + 1 whose bottom row is never handed off; 0 = none
+  // XCD queues (single-grid launches; nx <= 1: one global ticket counter).  A workgroup
+  // on XCD x (hardware XCC id, modulo nx) takes tickets from queue x, which hands out, in
+  // order, the tickets t with (t / seg) % nx == x: runs of seg consecutive bands share one
+  // XCD, and a band hands its bottom row to the next band of its run through that XCD's
+  // L2 instead of through memory.  Every queue needs a workgroup: the host uses queues
+  // only for launches of at least nx workgroups on a device whose dispatcher deals
+  // consecutive workgroups to consecutive XCDs.
+  int32_t nx, seg;
 };
 
 // Per (work item, compute wave) trace record, written when KArgs::trace is set:
@@ -60,11 +68,18 @@ constexpr int TRACE_WORDS = 8;
 //   [4] loader: wall clock when the chunk's loads were issued  [5] when they had landed
 //   [6] storer: wall clock when it began storing the chunk (or the last of a run of chunks
 //       stored together)  [7] when it released the chunk's H slot
-constexpr int CTRACE_WORDS = 8;
+//   [8] feeder (compute wave 0): wall clock when the T ring first held every position the
+//       chunk reads   [9] compute: wall clock when the chunk's T quads were validated
+//   [10] compute, record s: wall clock right after the handoff store of chunk
+//       s * CTRACE_EVERY + 4 was issued (the store that chunk s * CTRACE_EVERY of the next
+//       band waits for)   [11] unused
+constexpr int CTRACE_WORDS = 12;
 constexpr int CTRACE_EVERY = 8;   // one record per this many chunks
 
 // Control-word indices.
-enum { CTL_TICKET = 0, CTL_ERROR = 1, CTL_ABORT = 2, CTL_WORDS = 4 };
+// CTL_QUEUE + x: ticket counter of XCD queue x (x < MAX_XCD).
+constexpr int MAX_XCD = 8;
+enum { CTL_TICKET = 0, CTL_ERROR = 1, CTL_ABORT = 2, CTL_QUEUE = 8, CTL_WORDS = CTL_QUEUE + MAX_XCD };
 // Device error codes written to ctl[CTL_ERROR].
 enum { DEV_OK = 0, DEV_TIMEOUT = 1 };
 
@@ -86,6 +101,8 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
 // Traceback of a computed grid (see wf_traceback): dtype 0 = f32, 1 = i32, 2 = f64.
 hipError_t launch_traceback(int dtype, int rule, const void* H, int64_t ld, int64_t m, int64_t n, const void* top,
                             const void* left, int32_t* path, int64_t* length, hipStream_t stream);
+// Records the XCD (hardware XCC id) each of nwg one-wave workgroups runs on into out[0..nwg).
+hipError_t launch_xcc_probe(uint32_t* out, int nwg, hipStream_t stream);
 // LDS bytes per workgroup (for occupancy decisions).
 size_t lds_bytes(int W, int R);
 

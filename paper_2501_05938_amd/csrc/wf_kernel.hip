@@ -194,6 +194,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, ui
   return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
 }
 constexpr int CPOL_SC1 = 16;  // device-scope coherent access
+// The XCD (hardware XCC id, bits 3:0 of HW_REG_XCC_ID) the calling wave runs on.
+__device__ __forceinline__ uint32_t xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20); }
 
 typedef __attribute__((address_space(1))) uint32_t glb_u32;
 __device__ __forceinline__ glb_u32* G32(uint32_t* p) { return (glb_u32*)(void*)p; }
@@ -379,7 +381,7 @@ __device__ __forceinline__ void compute_chunk(
     int k, int G, int gT, int NCc, WaveLds* lds, WaveLds& L, WaveLds* C,
     __amdgpu_buffer_rsrc_t hand_out, const lds_u8* const (&cq)[4], lds_u8* const (&hq)[4], lds_u8* ct_base,
     bool lane63, int lane, const u4 (&cc)[R][4], u4 (&tc)[4], u4 (&cn)[R][4], u4 (&tn)[4], uint32_t& tprev_w,
-    T (&H)[R], T (&Hp)[R], T& Np, CtlSnap& snap, const KArgs& a, uint64_t* crec) {
+    T (&H)[R], T (&Hp)[R], T& Np, CtlSnap& snap, const KArgs& a, uint64_t* crec, bool hand_local) {
   const uint32_t SENT = Num<T>::SENT;
   const int pos = CHUNK * k;
   // Keep the chunk-start check (and the scalar copies of the control snapshot it takes)
@@ -464,6 +466,7 @@ __device__ __forceinline__ void compute_chunk(
     CBAR();
     if (lane == 0) st_ctl(&L.t_reset, (uint32_t)(pos + 64 * R + 4 * nq));
   }
+  if (rec && lane == 0) rec[9] = wall_clock64();
   read_chunk<R>(k + 1, cq, tr_base, cn, tn);
   const int hb = (k % H_SLOTS) * (R * SLAB);
   lds_u8* ct = ct_base + (pos & (RING_T - 1)) * 4;
@@ -520,8 +523,15 @@ __device__ __forceinline__ void compute_chunk(
     // Lane 60+q holds group 4k+q's quad.  Only positions [t_first(R), 4G) are written:
     // the others are never read by a consumer and stay at the sentinel.
     const int g = 4 * k + lane - 60;
-    if (lane >= 60 && g < G && (KIND != 0 || g >= 16 * R - 1))
-      __builtin_amdgcn_raw_buffer_store_b128(hand4, hand_out, 16 * g, 0, CPOL_SC1);
+    if (lane >= 60 && g < G && (KIND != 0 || g >= 16 * R - 1)) {
+      // A consumer on this XCD polls through the shared L2, which a plain store reaches;
+      // one on another XCD needs the store to go through to memory.
+      if (hand_local) __builtin_amdgcn_raw_buffer_store_b128(hand4, hand_out, 16 * g, 0, 0);
+      else __builtin_amdgcn_raw_buffer_store_b128(hand4, hand_out, 16 * g, 0, CPOL_SC1);
+    }
+    if (crec && (k % CTRACE_EVERY) == 4 && lane == 0)
+      ((__attribute__((address_space(1))) uint64_t*)(void*)crec)[(int64_t)(k / CTRACE_EVERY) * CTRACE_WORDS + 10] =
+          wall_clock64();
   }
 }
 
@@ -529,7 +539,7 @@ template <typename T, int RULE, int R, int CONS, bool MASK>
 __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLds& L, WaveLds* C,
                                              __amdgpu_buffer_rsrc_t hand_out, const lds_u8* const (&cq)[4],
                                              lds_u8* const (&hq)[4], int lane, const T (&Hinit)[R], const KArgs& a,
-                                             uint64_t* crec) {
+                                             uint64_t* crec, bool hand_local) {
   const int NCc = (4 * G + CHUNK - 1) / CHUNK;
   lds_u8* ct_base = CONS == 1 ? L8(C->tring) : nullptr;
   const bool lane63 = lane == 63;
@@ -561,7 +571,7 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   snap_ctl<CONS>(L, C, snap);
 #define WF_CHUNK(KIND, KK, CUR_C, CUR_T, NXT_C, NXT_T)                                                         \
   compute_chunk<T, RULE, R, KIND, CONS, MASK>(KK, G, gT, NCc, lds, L, C, hand_out, cq, hq, ct_base, lane63, lane,  \
-                                        CUR_C, CUR_T, NXT_C, NXT_T, tprev_w, H, Hp, Np, snap, a, crec)
+                                        CUR_C, CUR_T, NXT_C, NXT_T, tprev_w, H, Hp, Np, snap, a, crec, hand_local)
   int k = 0;
   // The first 4 R chunks (groups 0 .. 16 R - 1, where rows left of column 0 are masked;
   // a walk always has at least that many).
@@ -596,7 +606,7 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
 
 template <typename T, int RULE, int W, int R>
 __device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLds* lds, WaveRings<R>* rings, int w,
-                                             int lane, const KArgs& a, uint64_t* crec) {
+                                             int lane, const KArgs& a, uint64_t* crec, bool hand_local) {
   WaveLds& L = lds[w];
   const int64_t m = g.m, n = g.n;
   const int64_t row0 = (int64_t)band * (64 * R * W) + 64 * R * w;
@@ -632,18 +642,21 @@ __device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLd
   // no row padding (the inputs read for them are then the finite tail of the row above).
   const bool unmasked = !std::is_integral<T>::value && g.left == nullptr && g.ld_cost == n;
   if (lds_consumer) {
-    compute_walk<T, RULE, R, 1, true>(G, gT, lds, L, &lds[w + 1], __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec);
+    compute_walk<T, RULE, R, 1, true>(G, gT, lds, L, &lds[w + 1], __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec,
+                                      false);
   } else if (glob_consumer) {
     __amdgpu_buffer_rsrc_t hand_out = make_rsrc(g.hand + (int64_t)band * g.hand_ld, (uint32_t)(g.hand_ld * 4));
     if (unmasked)
-      compute_walk<T, RULE, R, 2, false>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec);
+      compute_walk<T, RULE, R, 2, false>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec, hand_local);
     else
-      compute_walk<T, RULE, R, 2, true>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec);
+      compute_walk<T, RULE, R, 2, true>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec, hand_local);
   } else {
     if (unmasked)
-      compute_walk<T, RULE, R, 0, false>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec);
+      compute_walk<T, RULE, R, 0, false>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec,
+                                         false);
     else
-      compute_walk<T, RULE, R, 0, true>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec);
+      compute_walk<T, RULE, R, 0, true>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec,
+                                        false);
   }
   if (a.trace && lane == 0) L.tr_end = __builtin_readcyclecounter();
 }
@@ -1133,7 +1146,8 @@ __device__ __forceinline__ void storer_band(const GridDesc& g, int band, WaveLds
 // that (the usual case); when a poll comes back wholly valid the producer is far
 // ahead and the next poll covers up to 64 quads.
 template <typename T, int RULE, int W, int R>
-__device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds* lds, int lane, const KArgs& a) {
+__device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds* lds, int lane, const KArgs& a,
+                                            uint32_t item) {
   const uint32_t SENT = Num<T>::SENT;
   const BandGeom B = band_geom<W, R>(g, band, 0);
   WaveLds& L = lds[0];
@@ -1141,6 +1155,15 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
   Watch t_idle;
   uint32_t polls = 0;
   const int t_pad = t_pad_end(B.G, R);
+  // Trace: the time each sampled chunk's T positions were all in the ring.
+  int next_s = 0;
+  auto note_fed = [&] {
+    if (!a.ctrace || lane != 0) return;
+    while (next_s < a.ctrace_nc && tw >= CHUNK * CTRACE_EVERY * next_s + 64 * R + CHUNK) {
+      chunk_rec(a, item, W, 0, CTRACE_EVERY * next_s)[8] = wall_clock64();
+      ++next_s;
+    }
+  };
   if (band == 0) {
     while (tw < t_pad) {
       int limit = (int)ld_ctl(&L.t_reset) + RING_T;
@@ -1164,6 +1187,7 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
           lds_st4(L8(L.tring) + (p & (RING_T - 1)) * 4, v);
         }
         tw += 4 * (nq < 64 ? nq : 64);
+        note_fed();
         __builtin_amdgcn_s_waitcnt(0xc07f);
         CBAR();
         if (lane == 0) st_ctl(&L.t_fed, (uint32_t)tw);
@@ -1212,6 +1236,7 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
     }
     if (lane >= off && lane < off + nvalid) lds_st4(L8(L.tring) + ((base + 4 * lane) & (RING_T - 1)) * 4, v);
     tw += 4 * nvalid;
+    note_fed();
     want = nvalid == nq - off ? 64 : SMALL;
     __builtin_amdgcn_s_waitcnt(0xc07f);
     CBAR();
@@ -1292,9 +1317,18 @@ void wf_sweep_kernel(KArgs a_in) {
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const Role role = role_of<W>(__builtin_amdgcn_readfirstlane(wave));
+  const uint32_t nx = a.nx > 1 ? (uint32_t)a.nx : 1u, seg = a.seg > 0 ? (uint32_t)a.seg : 1u;
+  // The queue of the XCD this workgroup runs on: every workgroup of a queue shares one L2.
+  const uint32_t xq = nx > 1 ? xcc_id() % nx : 0u;
   for (;;) {
     if (threadIdx.x == 0) {
-      uint32_t t = atomicAdd(&a.ctl[CTL_TICKET], 1u);
+      uint32_t t;
+      if (nx > 1) {
+        const uint32_t q = atomicAdd(&a.ctl[CTL_QUEUE + xq], 1u);
+        t = ((q / seg) * nx + xq) * seg + q % seg;
+      } else {
+        t = atomicAdd(&a.ctl[CTL_TICKET], 1u);
+      }
       if (ld_dev(a.ctl + CTL_ABORT)) t = 0xFFFFFFFFu;
       s_item = t;
     }
@@ -1332,11 +1366,14 @@ void wf_sweep_kernel(KArgs a_in) {
     }
     if (role.kind == R_COMPUTE) {
       uint64_t* crec = a.ctrace ? a.ctrace + ((int64_t)t * W + role.strip) * a.ctrace_nc * CTRACE_WORDS : nullptr;
-      compute_band<T, RULE, W, R>(gd, band, lds, rings, role.strip, lane, a, crec);
+      // The next band (ticket t + 1 of a single grid) runs on this XCD when both tickets
+      // fall in queue xq.
+      const bool hand_local = nx > 1 && ((t + 1u) / seg) % nx == xq;
+      compute_band<T, RULE, W, R>(gd, band, lds, rings, role.strip, lane, a, crec, hand_local);
     }
     else if (role.kind == R_LOADER) loader_band<W, R>(gd, band, lds, rings, role.strip, lane, a, t);
     else if (role.kind == R_STORER) storer_band<T, W, R>(gd, band, lds, rings, role.strip, lane, a, t);
-    else feeder_band<T, RULE, W, R>(gd, band, lds, lane, a);
+    else feeder_band<T, RULE, W, R>(gd, band, lds, lane, a, t);
     __syncthreads();
     if (a.trace && role.kind == R_COMPUTE && lane == 0) {
       const WaveLds& L = lds[role.strip];
@@ -1351,6 +1388,10 @@ void wf_sweep_kernel(KArgs a_in) {
       r[7] = L.tr_wall;
     }
   }
+}
+
+__global__ void xcc_probe_kernel(uint32_t* out) {
+  if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
@@ -2007,6 +2048,12 @@ hipError_t launch_traceback(int dtype, int rule, const void* H, int64_t ld, int6
     return hipErrorInvalidValue;
   }
 #undef WF_TB
+  return hipGetLastError();
+}
+
+hipError_t launch_xcc_probe(uint32_t* out, int nwg, hipStream_t stream) {
+  if (nwg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(xcc_probe_kernel, dim3((unsigned)nwg), dim3(64), 0, stream, out);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include "wf_host.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -57,6 +58,9 @@ wf_status wfh::set_device(wf_ctx* ctx) {
 }
 
 // ------------------------------------------------------------------ slots
+// Set once a launch with XCD queues timed out: no later launch uses them.
+static std::atomic<bool> xcd_off{false};
+
 // Reads the device status of a slot's last launch.  wait: block until it is done.
 // After a watchdog abort the slot is marked for re-arming; the refill happens on the
 // stream of the slot's next launch (ensure_hand), so it is ordered before that launch.
@@ -72,6 +76,9 @@ static wf_status harvest(Slot& s, bool wait) {
   if (*s.host_err != DEV_OK) {
     *s.host_err = DEV_OK;
     s.needs_rearm = true;
+    // A queue without a workgroup would stall its bands until the watchdog fires: after
+    // a timed-out launch that used XCD queues, no later launch uses them.
+    if (s.xcd_queues) xcd_off.store(true);
     return fail(WF_ETIMEDOUT, "device watchdog fired: a wait for a neighbouring band exceeded the limit "
                               "(NaN or reserved-value inputs, or an oversubscribed device)");
   }
@@ -168,7 +175,8 @@ static wf_status ensure_buf(T** p, size_t* cap, size_t need) {
   return WF_OK;
 }
 
-static wf_status finish_launch(Slot& s, hipStream_t stream) {
+static wf_status finish_launch(Slot& s, hipStream_t stream, bool xcd_queues = false) {
+  s.xcd_queues = xcd_queues;
   WF_HIP(hipMemcpyAsync(s.host_err, s.ctl + CTL_ERROR, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
   WF_HIP(hipEventRecord(s.done, stream));
   s.pending = true;
@@ -286,6 +294,47 @@ size_t wfh::hand_elems(const wf_problem* p, int bs) {
   return nb > 1 ? (size_t)(nb - 1) * (size_t)hand_ld_for(p->n, shape_rows_per_lane(bs)) * words : 0;
 }
 
+void wfh::xcd_queues(const wf_ctx* ctx, KArgs& a, int nwg, int dtype) {
+  const int nx = ctx->nx;
+  if (nx < 2 || nwg < nx || dtype == WF_F64 || a.grids || xcd_off.load()) return;
+  // Runs of seg bands per XCD: at most one band per workgroup of the XCD's queue at a
+  // time, and the grid's bands spread over all XCDs.
+  const int64_t per_xcd = (a.nitems + nx - 1) / nx;
+  a.nx = nx;
+  a.seg = (int32_t)std::max<int64_t>(1, std::min<int64_t>(per_xcd, nwg / nx));
+}
+
+// Which XCD each workgroup of a launch runs on, from a probe launch: XCD queues are used
+// only when consecutive workgroups run on consecutive XCDs (modulo nx, from wherever the
+// dispatcher's turn stands), as a whole-chip (SPX) device deals them, so that a launch of
+// at least nx workgroups has one on every XCD.
+static void probe_xcds(wf_ctx* ctx) {
+  ctx->nx = 1;
+  if (const char* e = std::getenv("WF_XCD_QUEUES"))
+    if (std::atoi(e) == 0) return;
+  const int nwg = ctx->num_cus * 2;
+  uint32_t* d = nullptr;
+  if (hipMalloc(&d, (size_t)nwg * sizeof(uint32_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  std::vector<uint32_t> h((size_t)nwg, 0u);
+  const bool ok = launch_xcc_probe(d, nwg, nullptr) == hipSuccess &&
+                  hipMemcpy(h.data(), d, (size_t)nwg * sizeof(uint32_t), hipMemcpyDeviceToHost) == hipSuccess;
+  (void)hipFree(d);
+  if (!ok) {
+    (void)hipGetLastError();
+    return;
+  }
+  uint32_t top = 0;
+  for (uint32_t v : h) top = std::max(top, v);
+  const int nx = (int)top + 1;
+  if (nx < 2 || nx > MAX_XCD) return;
+  for (int i = 0; i < nwg; ++i)
+    if (h[(size_t)i] != (h[0] + (uint32_t)i) % (uint32_t)nx) return;
+  ctx->nx = nx;
+}
+
 KArgs wfh::base_args(wf_ctx* ctx, uint32_t* ctl, int64_t nitems) {
   KArgs a;
   std::memset(&a, 0, sizeof a);
@@ -396,6 +445,7 @@ extern "C" wf_status wf_init(int device, wf_ctx** out) {
   }
   wf_status st = set_device(ctx.get());
   if (st != WF_OK) return st;
+  probe_xcds(ctx.get());
   // wf_solve_noalloc's slot: its control words and handoff rows are the device's fixed
   // array, looked up here with the device current; its pinned error word and event are
   // made now so that the entry point itself allocates nothing.
@@ -509,6 +559,7 @@ static wf_status solve_one(wf_ctx* ctx, const wf_problem* p, int bs, int max_wgs
   const int resident = ctx->num_cus * wgs_per_cu(bs, p->dtype);
   int nwg = (int)std::min<int64_t>(a.nitems, resident);
   if (max_wgs > 0) nwg = std::min(nwg, max_wgs);
+  xcd_queues(ctx, a, nwg, p->dtype);
   // Optional trace (profiling hook): WF_TRACE_FILE=<path> makes wf_solve synchronous
   // and writes TRACE_WORDS uint64 per (band, compute wave) to <path>.
   const char* trace_file = std::getenv("WF_TRACE_FILE");
@@ -549,7 +600,7 @@ static wf_status solve_one(wf_ctx* ctx, const wf_problem* p, int bs, int max_wgs
       std::fclose(f);
     }
   }
-  return finish_launch(*s, stream);
+  return finish_launch(*s, stream, a.nx > 1);
 }
 
 static wf_status solve_entry(wf_ctx* ctx, const wf_problem* p, const wf_tuning* t, void* stream_) {
@@ -608,10 +659,11 @@ extern "C" wf_status wf_solve_noalloc(wf_ctx* ctx, const wf_problem* p, void* st
   a.g0 = make_desc(p, bs, s.hand);
   a.nitems = a.g0.nbands;
   const int nwg = (int)std::min<int64_t>(a.nitems, (int64_t)ctx->num_cus * wgs_per_cu(bs, p->dtype));
+  xcd_queues(ctx, a, nwg, p->dtype);
   WF_HIP(launch_noalloc_prep(s.ctl, s.needs_rearm, s.hand, sentinel_of(p->dtype), (int64_t)need, stream));
   s.needs_rearm = false;
   WF_HIP(launch_shape(p->dtype, p->rule, bs, nwg, a, stream));
-  return finish_launch(s, stream);
+  return finish_launch(s, stream, a.nx > 1);
 }
 
 extern "C" wf_status wf_traceback(wf_ctx* ctx, const wf_problem* p, int32_t* path, int64_t* length, void* stream) {
