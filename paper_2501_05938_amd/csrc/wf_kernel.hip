@@ -81,10 +81,12 @@ struct alignas(16) WaveLds {
   uint32_t tring[RING_T];
   uint32_t c_ready;   // chunks of c committed to cring (IO -> compute)
   uint32_t h_done;    // positions of H stored out of hring (IO -> compute)
+  uint32_t t_fed;     // T positions below this are in the ring (feeder or the compute wave above -> this
+                      // wave; wave 0's also -> storer)
   uint32_t progress;  // (signed) position of the chunk being computed: earlier chunks are done (compute -> IO)
-  uint32_t t_reset;   // T positions below this are re-armed (by this wave; -> producer); slots < t_reset + RING_T writable
+  uint32_t t_reset;   // T positions below this have been read (this wave -> feeder or the compute wave
+                      // above): slots of positions < t_reset + RING_T are writable
   uint32_t abort;     // workgroup abort flag (only lds[0].abort is used)
-  uint32_t t_fed;     // wave 0: T positions copied into the ring by the feeder (feeder -> storer)
   uint32_t pad[2];
   // trace counters (written only when KArgs::trace is set)
   uint64_t tr_start, tr_first, tr_end, tr_wall;
@@ -180,6 +182,8 @@ __device__ __forceinline__ void st_ctl(uint32_t* p, uint32_t v) {
 }
 typedef __attribute__((address_space(3))) unsigned char lds_u8;
 typedef __attribute__((address_space(3))) u4 lds_u4;
+typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) u2 lds_u2;
 template <class P> __device__ __forceinline__ lds_u8* L8(P* p) { return (lds_u8*)(void*)p; }
 __device__ __forceinline__ u4 lds_ld4(const lds_u8* p) { return *(const lds_u4*)p; }
 __device__ __forceinline__ u4 lds_ld4_fresh(const lds_u8* p) { return *(const volatile lds_u4*)p; }
@@ -275,19 +279,6 @@ __device__ __forceinline__ glb_u64* chunk_rec(const KArgs& a, uint32_t item, int
 }
 
 // ------------------------------------------------------------ compute wave
-// Check for a launch abort (workgroup flag, then occasionally the device flag).
-__device__ __forceinline__ bool aborting(WaveLds* lds, uint32_t* ctl, uint64_t watchdog_ticks, uint32_t spins) {
-  if (ld_ctl(&lds[0].abort)) return true;
-  // s_sleep 1 is 64 clocks; the spin count bounds the wait to roughly watchdog_ticks.
-  if ((uint64_t)spins * 64u > watchdog_ticks * 24u) {
-    st_ctl(&lds[0].abort, 1u);
-    __hip_atomic_store(G32(ctl + CTL_ERROR), (uint32_t)DEV_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(G32(ctl + CTL_ABORT), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
-  }
-  return false;
-}
-
 // Rare path of an inline spin, called every few thousand polls.  Returns the start
 // of the idle period (taking it now when t0 is 0), or 0 when the wait must end: the
 // launch is aborting, or the wait has outlasted the watchdog (then it raises the abort).
@@ -305,50 +296,40 @@ __device__ __noinline__ uint64_t spin_check(WL* lds, uint32_t* ctl, uint64_t wat
   return t0;
 }
 
-// Spin until the T quad at `tp` has been written.  Returns false if the launch is aborting.
-template <typename T>
-__device__ __noinline__ u4 wait_quad(const lds_u8* tp, WaveLds* lds, uint32_t* ctl, uint64_t watchdog_ticks,
-                                     uint64_t* wait_acc) {
-  uint32_t spins = 0;
-  const uint64_t c0 = wait_acc ? __builtin_readcyclecounter() : 0;
-  u4 q;
-  do {
-    __builtin_amdgcn_s_sleep(1);
-    q = lds_ld4_fresh(tp);
-    if ((++spins & 1023u) == 0u && aborting(lds, ctl, watchdog_ticks, spins)) break;
-  } while (Num<T>::probe(q) == Num<T>::SENT);
-  if (wait_acc) *wait_acc += __builtin_readcyclecounter() - c0;
-  return q;
-}
-
 // Reads of chunk kn's inputs for one lane: its 4 R c quads (cq[q]: this lane's logical
-// quad q in slab 0 of slot 0) and its four T quads (the T ring is fed up to the
+// quad q in slab 0 of slot 0), and the chunk's four T quads (the T ring is fed up to the
 // padding past the band's last position, so every chunk has four).  A read past the
 // last chunk only picks up unused stale data.
 template <int R>
-__device__ __forceinline__ void read_chunk(int kn, const lds_u8* const (&cq)[4], const lds_u8* tr_base,
-                                           u4 (&c)[R][4], u4 (&t)[4]) {
+__device__ __forceinline__ void read_c(int kn, const lds_u8* const (&cq)[4], u4 (&c)[R][4]) {
   const int sb = (kn % C_SLOTS) * (R * SLAB);
 #pragma unroll
   for (int s = 0; s < R; ++s)
 #pragma unroll
     for (int q = 0; q < 4; ++q) c[s][q] = lds_ld4(cq[q] + sb + s * SLAB);
+}
+template <int R>
+__device__ __forceinline__ void read_t(int kn, const lds_u8* tr_base, u4 (&t)[4]) {
   const int tpos = (CHUNK * kn + 64 * R) & (RING_T - 1);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) t[q] = lds_ld4(tr_base + (tpos + 4 * q) * 4);
+  for (int q = 0; q < 4; ++q) t[q] = lds_ld4_fresh(tr_base + (tpos + 4 * q) * 4);
 }
 
 // Control words a chunk start checks, read ahead of time.  The counters only grow, so
 // a check that passes on values read earlier also passes on current ones; one that
 // fails falls back to waiting on fresh reads.  This wave's words are read with one
 // 16-byte LDS read and kept in vector registers until the check: taking scalar copies
-// right after the read would make the walk wait for it mid-chunk.
+// right after the read would make the walk wait for it mid-chunk, and so would handing
+// any of the read's registers to the walk while the read is in flight (a register may
+// not be rewritten before the read that targets it has landed), hence keep_live().
 struct CtlSnap {
-  u4 own;                 // c_ready, h_done, progress, t_reset of this wave
+  u4 own;                 // c_ready, h_done, t_fed, progress of this wave
   uint32_t cons_t_reset;  // the consumer wave's t_reset (CONS == 1)
+  __device__ void keep_live() { asm volatile("" ::"v"(own)); }
 };
-static_assert(offsetof(WaveLds, c_ready) % 16 == 0 && offsetof(WaveLds, h_done) == offsetof(WaveLds, c_ready) + 4,
-              "c_ready and h_done open an aligned quad");
+static_assert(offsetof(WaveLds, c_ready) % 16 == 0 && offsetof(WaveLds, h_done) == offsetof(WaveLds, c_ready) + 4 &&
+                  offsetof(WaveLds, t_fed) == offsetof(WaveLds, c_ready) + 8,
+              "c_ready, h_done and t_fed open an aligned quad");
 
 template <int CONS>
 __device__ __forceinline__ void snap_ctl(WaveLds& L, WaveLds* C, CtlSnap& s) {
@@ -363,17 +344,19 @@ __device__ __forceinline__ void snap_ctl(WaveLds& L, WaveLds* C, CtlSnap& s) {
 // last sub-row by DPP (lane 0: the T value), its NW is the previous step's N; sub-row
 // s > 0 takes N and NW from sub-row s-1 of the same lane (its values one and two steps
 // back).  The R cells of a step depend only on earlier steps, so they run side by side.
-// The T quads of the chunk are validated together at its start (the group loop then runs
-// without branches): when the producer is not that far yet, the chunk waits for the
-// chunk's last quad, which the producer writes after the others.
+// The chunk's T quads are read near the end of the previous chunk, right after the
+// control snapshot, and the chunk start checks the snapshot's count of fed T positions
+// (the group loop then runs without branches): when the ring did not yet hold them, the
+// chunk waits for the count and reads the quads again.
 // KIND 0: the first 4 R chunks, where rows left of column 0 keep their boundary value;
 // KIND 1: every later chunk.  MASK: KIND 0 chunks select the kept value per cell; without
 // it (floating point, default left boundary, no row padding) a cell left of column 0 is
 // computed like any other: its own and its upper neighbours' values are then all
 // "absent" (infinite), the finite input added to an infinity gives the same infinity,
-// and every such cell holds the absent value, which is its boundary value.  The T ring is fed past the band's last T position with
-// absent values, so KIND 1 chunks read and check all four quads; groups past the last
-// one (g >= G) compute cells right of the grid, which nothing stores or reads.
+// and every such cell holds the absent value, which is its boundary value.  The T ring
+// is fed past the band's last T position with absent values, so every chunk reads four
+// quads; groups past the last one (g >= G) compute cells right of the grid, which
+// nothing stores or reads.
 // CONS: 0 = no consumer, 1 = the next compute wave (LDS), 2 = the next band (global
 // handoff row).
 template <typename T, int RULE, int R, int KIND, int CONS, bool MASK>
@@ -382,7 +365,6 @@ __device__ __forceinline__ void compute_chunk(
     __amdgpu_buffer_rsrc_t hand_out, const lds_u8* const (&cq)[4], lds_u8* const (&hq)[4], lds_u8* ct_base,
     bool lane63, int lane, const u4 (&cc)[R][4], u4 (&tc)[4], u4 (&cn)[R][4], u4 (&tn)[4], uint32_t& tprev_w,
     T (&H)[R], T (&Hp)[R], T& Np, CtlSnap& snap, const KArgs& a, uint64_t* crec, bool hand_local) {
-  const uint32_t SENT = Num<T>::SENT;
   const int pos = CHUNK * k;
   // Keep the chunk-start check (and the scalar copies of the control snapshot it takes)
   // from being scheduled into the previous chunk's walk.
@@ -394,27 +376,39 @@ __device__ __forceinline__ void compute_chunk(
           ? (__attribute__((address_space(1))) uint64_t*)(void*)(crec + (int64_t)(k / CTRACE_EVERY) * CTRACE_WORDS)
           : nullptr;
   if (rec && lane == 0) rec[0] = wall_clock64();
-  // Chunk start: publish progress, then wait until the c ring holds the next chunk, the
-  // H slot is free, this wave's T slots up to the next chunk's quads hold the current lap,
-  // and the consumer's T slots for this chunk are re-armed.
+  // Chunk start: publish progress (and, as the compute wave above the consumer, how far
+  // the consumer's T ring is written: every position of the earlier chunks), then wait
+  // until the c ring holds the next chunk, the H slot is free, the T ring holds this
+  // chunk's positions, and the consumer's T slots for this chunk have been read.
   CBAR();
-  if (lane == 0) st_ctl(&L.progress, (uint32_t)pos);
+  if (lane == 0) {
+    st_ctl(&L.progress, (uint32_t)pos);
+    if (CONS == 1) st_ctl(&C->t_fed, (uint32_t)pos);
+  }
+  const lds_u8* tr_base = L8(L.tring);
   {
     const int need_c = k + 2 < NCc ? k + 2 : NCc;
     const int need_h = pos + CHUNK - H_SLOTS * CHUNK;
+    const int need_f = pos + 64 * R + CHUNK;
     const int need_t = pos + CHUNK - RING_T;
     auto ok = [&](const CtlSnap& v) {
       return (int)__builtin_amdgcn_readfirstlane(v.own.x) >= need_c &&
              (int)__builtin_amdgcn_readfirstlane(v.own.y) >= need_h &&
+             (int)__builtin_amdgcn_readfirstlane(v.own.z) >= need_f &&
              (CONS != 1 || (int)v.cons_t_reset >= need_t);
     };
+    snap.keep_live();
     if (!ok(snap)) {
       const uint64_t c0 = a.trace ? __builtin_readcyclecounter() : 0;
       if (rec && lane == 0) {
         rec[3] = ((int)snap.own.x < need_c ? 1u : 0u) | ((int)snap.own.y < need_h ? 2u : 0u) |
-                 (CONS == 1 && (int)snap.cons_t_reset < need_t ? 8u : 0u);
+                 ((int)snap.own.z < need_f ? 4u : 0u) | (CONS == 1 && (int)snap.cons_t_reset < need_t ? 8u : 0u);
       }
       wait_until<false>([&] { snap_ctl<CONS>(L, C, snap); return ok(snap); }, lds, a);
+      // The chunk's T quads were read before the ring held them all: read them again
+      // (after the snapshot that shows they are there, so they are the fed values).
+      read_t<R>(k, tr_base, tc);
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the re-read quads are in registers
       if (a.trace && lane == 0) L.tr_chunk_wait += __builtin_readcyclecounter() - c0;
     }
     if (rec && lane == 0) {
@@ -423,51 +417,11 @@ __device__ __forceinline__ void compute_chunk(
     }
   }
   CBAR();
-  const lds_u8* tr_base = L8(L.tring);
-  const int tpos = (pos + 64 * R) & (RING_T - 1);  // T ring position of group 4k's quad
-  // Validate the chunk's T quads (all four; in the first 4 R chunks, those of groups
-  // below gT, whose quads hold columns of the grid).  All four words of a quad
-  // are checked: a 16-byte LDS read racing a 16-byte write from another wave may see
-  // part of it.  All lanes read the same quads, so the test is wave-uniform.
-  if (KIND == 1 || 4 * k < gT) {
-    uint32_t pr = Num<T>::probe(tc[0]);
-#pragma unroll
-    for (int q = 1; q < 4; ++q)
-      if (KIND == 1 || 4 * k + q < gT) pr = Num<T>::combine(pr, Num<T>::probe(tc[q]));
-    if (__builtin_expect(__builtin_amdgcn_readfirstlane(pr) == SENT, 0)) {
-      // Wait (one lane polling) for the chunk's last quad below gT, then re-read them all.
-      int ql = 3;
-      if (KIND != 1)
-        while (ql > 0 && 4 * k + ql >= gT) --ql;
-      const lds_u8* tw = tr_base + (tpos + 4 * ql) * 4;
-      const uint64_t c0 = a.trace ? __builtin_readcyclecounter() : 0;
-      uint64_t t0 = 0;
-      uint32_t spins = 0;
-      for (;;) {
-        uint32_t p1 = SENT;
-        if (lane == 0) p1 = Num<T>::probe(lds_ld4_fresh(tw));
-        if (__builtin_amdgcn_readfirstlane(p1) != SENT) break;
-        if ((++spins & 2047u) == 0u && (t0 = spin_check(lds, a.ctl, a.watchdog_ticks, t0)) == 0) break;
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (KIND == 1 || 4 * k + q < gT) tc[q] = lds_ld4_fresh(tr_base + (tpos + 4 * q) * 4);
-      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the re-read quads are in registers
-      if (a.trace && lane == 0) L.tr_t_wait += __builtin_readcyclecounter() - c0;
-    }
-    // The chunk's quads are in registers: re-arm their slots for the next lap (lane q
-    // writes quad q) and let the producer reuse them.  LDS accesses of one wave complete
-    // in order, so the producer sees the sentinels before the new limit.
-    const int nq = KIND == 1 ? 4 : (gT - 4 * k < 4 ? gT - 4 * k : 4);
-    if (lane < nq) {
-      const u4 s4 = {SENT, SENT, SENT, SENT};
-      lds_st4(L8(L.tring) + (tpos + 4 * lane) * 4, s4);
-    }
-    CBAR();
-    if (lane == 0) st_ctl(&L.t_reset, (uint32_t)(pos + 64 * R + 4 * nq));
-  }
+  // The chunk's T quads are in registers: let the feeder (or the compute wave above)
+  // reuse their slots.
+  if (lane == 0) st_ctl(&L.t_reset, (uint32_t)(pos + 64 * R + CHUNK));
   if (rec && lane == 0) rec[9] = wall_clock64();
-  read_chunk<R>(k + 1, cq, tr_base, cn, tn);
+  read_c<R>(k + 1, cq, cn);
   const int hb = (k % H_SLOTS) * (R * SLAB);
   lds_u8* ct = ct_base + (pos & (RING_T - 1)) * 4;
   // Bottom-row quads of the chunk for the next band, gathered into lanes 60..63 (lane 63
@@ -477,8 +431,13 @@ __device__ __forceinline__ void compute_chunk(
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int g = 4 * k + q;
-    // The next chunk start's checks, read while this last group runs.
-    if (q == 3) snap_ctl<CONS>(L, C, snap);
+    // The next chunk start's checks, read while this last group runs, then the next
+    // chunk's T quads: LDS accesses of one wave complete in order, so when the
+    // snapshot shows the ring holds them, these reads returned them.
+    if (q == 3) {
+      snap_ctl<CONS>(L, C, snap);
+      read_t<R>(k + 1, tr_base, tn);
+    }
     const u4 tv = tc[q];
     const uint32_t tk[4] = {tprev_w, tv.x, tv.y, tv.z};
     if (KIND == 1 || g < gT) tprev_w = tv.w;
@@ -544,19 +503,19 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   lds_u8* ct_base = CONS == 1 ? L8(C->tring) : nullptr;
   const bool lane63 = lane == 63;
   constexpr int TF = t_first(R);
-  // First T quad: columns -3..0 of the row above (.z is the corner, .w column 0).
-  u4 tprev = lds_ld4_fresh(L8(L.tring) + TF * 4);
-  if (Num<T>::probe(tprev) == Num<T>::SENT)
-    tprev = wait_quad<T>(L8(L.tring) + TF * 4, lds, a.ctl, a.watchdog_ticks, nullptr);
+  // First T quad: columns -3..0 of the row above (.z is the corner, .w column 0), read
+  // once the ring holds it.
+  {
+    const uint64_t c0 = a.trace ? __builtin_readcyclecounter() : 0;
+    wait_until<false>([&] { return (int)ld_ctl(&L.t_fed) >= TF + 4; }, lds, a);
+    if (a.trace && lane == 0) L.tr_t_wait += __builtin_readcyclecounter() - c0;
+  }
+  const u4 tprev = lds_ld4_fresh(L8(L.tring) + TF * 4);
   if (a.trace && lane == 0) L.tr_first = __builtin_readcyclecounter();
   // NW of step 0: the corner for lane 0; for the other lanes the row above's column -1,
   // which lies left of the grid (absent by default; selected away when masked).
   T Np = lane == 0 ? from_bits<T>(tprev.z) : Num<T>::template absent<RULE>();
   uint32_t tprev_w = tprev.w;
-  if (lane == 0) {
-    const u4 s4 = {Num<T>::SENT, Num<T>::SENT, Num<T>::SENT, Num<T>::SENT};
-    lds_st4(L8(L.tring) + TF * 4, s4);
-  }
   T H[R], Hp[R];
 #pragma unroll
   for (int sr = 0; sr < R; ++sr) H[sr] = Hp[sr] = Hinit[sr];
@@ -564,11 +523,10 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   u4 cA[R][4], tA[4], cB[R][4], tB[4];
   wait_until<false>([&] { return ld_ctl(&L.c_ready) >= 1u; }, lds, a);
   CBAR();
-  read_chunk<R>(0, cq, L8(L.tring), cA, tA);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) tB[q] = tA[q];
+  read_c<R>(0, cq, cA);
   CtlSnap snap;
   snap_ctl<CONS>(L, C, snap);
+  read_t<R>(0, L8(L.tring), tA);  // after the snapshot, as in every chunk
 #define WF_CHUNK(KIND, KK, CUR_C, CUR_T, NXT_C, NXT_T)                                                         \
   compute_chunk<T, RULE, R, KIND, CONS, MASK>(KK, G, gT, NCc, lds, L, C, hand_out, cq, hq, ct_base, lane63, lane,  \
                                         CUR_C, CUR_T, NXT_C, NXT_T, tprev_w, H, Hp, Np, snap, a, crec, hand_local)
@@ -601,6 +559,8 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
     st_ctl(&L.progress, (uint32_t)(4 * G));
     // Every T position this walk reads has been consumed: release the producer's tail.
     st_ctl(&L.t_reset, (uint32_t)t_pad);
+    // The consumer's ring holds every position it reads, padding included.
+    if (CONS == 1) st_ctl(&C->t_fed, (uint32_t)t_pad);
   }
 }
 
