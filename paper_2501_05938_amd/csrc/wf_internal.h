@@ -62,7 +62,8 @@ struct KArgs {
 constexpr int TRACE_WORDS = 8;
 // Per-chunk trace record (compute waves, when KArgs::ctrace is set; chunks
 // 0, CTRACE_EVERY, 2*CTRACE_EVERY, ...):
-//   [0] wall clock on reaching the chunk start   [1] wall clock when its wait ended
+//   [0] wall clock on reaching the chunk start   [1] wall clock when its start conditions
+//       were seen to hold (checked at the end of the chunk before)
 //   [2] cycles spent so far waiting for top-boundary quads (needs KArgs::trace)
 //   [3] which conditions were not met on arrival: 1 c ring, 2 H ring, 8 consumer's T ring
 //   [4] loader: wall clock when the chunk's loads were issued  [5] when they had landed

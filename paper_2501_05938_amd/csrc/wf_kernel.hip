@@ -83,10 +83,10 @@ struct alignas(16) WaveLds {
   uint32_t h_done;    // positions of H stored out of hring (IO -> compute)
   uint32_t t_fed;     // T positions below this are in the ring (feeder or the compute wave above -> this
                       // wave; wave 0's also -> storer)
+  uint32_t abort;     // workgroup abort flag (only lds[0].abort is used)
   uint32_t progress;  // (signed) position of the chunk being computed: earlier chunks are done (compute -> IO)
   uint32_t t_reset;   // T positions below this have been read (this wave -> feeder or the compute wave
                       // above): slots of positions < t_reset + RING_T are writable
-  uint32_t abort;     // workgroup abort flag (only lds[0].abort is used)
   uint32_t pad[2];
   // trace counters (written only when KArgs::trace is set)
   uint64_t tr_start, tr_first, tr_end, tr_wall;
@@ -184,6 +184,8 @@ typedef __attribute__((address_space(3))) unsigned char lds_u8;
 typedef __attribute__((address_space(3))) u4 lds_u4;
 typedef uint32_t u2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) u2 lds_u2;
+typedef uint32_t u3 __attribute__((ext_vector_type(3)));
+typedef __attribute__((address_space(3))) u3 lds_u3;
 template <class P> __device__ __forceinline__ lds_u8* L8(P* p) { return (lds_u8*)(void*)p; }
 __device__ __forceinline__ u4 lds_ld4(const lds_u8* p) { return *(const lds_u4*)p; }
 __device__ __forceinline__ u4 lds_ld4_fresh(const lds_u8* p) { return *(const volatile lds_u4*)p; }
@@ -310,31 +312,80 @@ __device__ __forceinline__ void read_c(int kn, const lds_u8* const (&cq)[4], u4 
 }
 template <int R>
 __device__ __forceinline__ void read_t(int kn, const lds_u8* tr_base, u4 (&t)[4]) {
-  const int tpos = (CHUNK * kn + 64 * R) & (RING_T - 1);
+  // The chunk's 16 positions are contiguous in the ring (it holds a whole number of chunks).
+  const lds_u8* tb = tr_base + ((CHUNK * kn + 64 * R) & (RING_T - 1)) * 4;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) t[q] = lds_ld4_fresh(tr_base + (tpos + 4 * q) * 4);
+  for (int q = 0; q < 4; ++q) t[q] = lds_ld4_fresh(tb + 16 * q);
 }
 
 // Control words a chunk start checks, read ahead of time.  The counters only grow, so
 // a check that passes on values read earlier also passes on current ones; one that
-// fails falls back to waiting on fresh reads.  This wave's words are read with one
-// 16-byte LDS read and kept in vector registers until the check: taking scalar copies
-// right after the read would make the walk wait for it mid-chunk, and so would handing
-// any of the read's registers to the walk while the read is in flight (a register may
-// not be rewritten before the read that targets it has landed), hence keep_live().
+// fails falls back to waiting on fresh reads.  This wave's three words are read with one
+// 12-byte LDS read and kept in vector registers until the check: taking scalar copies
+// right after the read would make the walk wait for it mid-chunk, and so would a wider
+// read whose unused register the compiler hands to the walk while the read is in flight
+// (a register may not be rewritten before the read that targets it has landed).
 struct CtlSnap {
-  u4 own;                 // c_ready, h_done, t_fed, progress of this wave
+  u3 own;                 // c_ready, h_done, t_fed of this wave
   uint32_t cons_t_reset;  // the consumer wave's t_reset (CONS == 1)
-  __device__ void keep_live() { asm volatile("" ::"v"(own)); }
 };
 static_assert(offsetof(WaveLds, c_ready) % 16 == 0 && offsetof(WaveLds, h_done) == offsetof(WaveLds, c_ready) + 4 &&
                   offsetof(WaveLds, t_fed) == offsetof(WaveLds, c_ready) + 8,
               "c_ready, h_done and t_fed open an aligned quad");
+static_assert(offsetof(WaveLds, progress) % 8 == 0 && offsetof(WaveLds, t_reset) == offsetof(WaveLds, progress) + 4,
+              "progress and t_reset form an aligned pair (published with one store)");
 
 template <int CONS>
 __device__ __forceinline__ void snap_ctl(WaveLds& L, WaveLds* C, CtlSnap& s) {
-  s.own = lds_ld4_fresh(L8(&L.c_ready));
+  s.own = *(const volatile lds_u3*)L8(&L.c_ready);
   s.cons_t_reset = CONS == 1 ? ld_ctl(&C->t_reset) : 0u;
+}
+
+// Sampled per-chunk trace record of a compute wave's chunk k (crec: the wave's records),
+// or null.
+__device__ __forceinline__ glb_u64* chunk_trace(uint64_t* crec, int k) {
+  return crec && (k % CTRACE_EVERY) == 0 ? (glb_u64*)(void*)(crec + (int64_t)(k / CTRACE_EVERY) * CTRACE_WORDS)
+                                         : nullptr;
+}
+
+// Whether chunk k may start: the c ring holds chunk k + 1 (read during chunk k), chunk
+// k's H slot is free, the T ring holds chunk k's positions, and (CONS == 1) the consumer
+// has read the positions that chunk k's groups overwrite in its ring.  The check runs on
+// a snapshot of the control words read before chunk k's T quads `t`; the snapshot's
+// words are the same in every lane, so it is a vector compare per word and one branch on
+// the combined lane mask.  When it fails, the wave waits on fresh snapshots and reads
+// `t` again (after the snapshot that shows the ring holds them, so they are the fed
+// values).  Run at the end of chunk k - 1, so that no snapshot stays live across the
+// walk's loop edge (the compiler would move it to scalar registers, which makes the
+// walk wait for the read mid-chunk).
+template <int R, int CONS>
+__device__ __forceinline__ void chunk_gate(int k, int NCc, WaveLds* lds, WaveLds& L, WaveLds* C, CtlSnap& snap,
+                                           u4 (&t)[4], const KArgs& a, int lane, glb_u64* rec) {
+  const int pos = CHUNK * k;
+  const int need_c = k + 2 < NCc ? k + 2 : NCc;
+  const int need_h = pos + CHUNK - H_SLOTS * CHUNK;
+  const int need_f = pos + 64 * R + CHUNK;
+  const int need_t = pos + CHUNK - RING_T;
+  auto ok = [&](const CtlSnap& v) {
+    const bool p = ((int)v.own.x >= need_c) & ((int)v.own.y >= need_h) & ((int)v.own.z >= need_f) &
+                   (CONS != 1 || (int)v.cons_t_reset >= need_t);
+    return __builtin_amdgcn_ballot_w64(p) != 0ull;
+  };
+  if (!ok(snap)) {
+    const uint64_t c0 = a.trace ? __builtin_readcyclecounter() : 0;
+    if (rec && lane == 0) {
+      rec[3] = ((int)snap.own.x < need_c ? 1u : 0u) | ((int)snap.own.y < need_h ? 2u : 0u) |
+               ((int)snap.own.z < need_f ? 4u : 0u) | (CONS == 1 && (int)snap.cons_t_reset < need_t ? 8u : 0u);
+    }
+    wait_until<false>([&] { snap_ctl<CONS>(L, C, snap); return ok(snap); }, lds, a);
+    read_t<R>(k, L8(L.tring), t);
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the re-read quads are in registers
+    if (a.trace && lane == 0) L.tr_chunk_wait += __builtin_readcyclecounter() - c0;
+  }
+  if (rec && lane == 0) {
+    rec[1] = wall_clock64();
+    rec[2] = L.tr_t_wait;
+  }
 }
 
 // One chunk (4 groups of 4 steps) of the walk, computed from the inputs read during the
@@ -345,9 +396,10 @@ __device__ __forceinline__ void snap_ctl(WaveLds& L, WaveLds* C, CtlSnap& s) {
 // s > 0 takes N and NW from sub-row s-1 of the same lane (its values one and two steps
 // back).  The R cells of a step depend only on earlier steps, so they run side by side.
 // The chunk's T quads are read near the end of the previous chunk, right after the
-// control snapshot, and the chunk start checks the snapshot's count of fed T positions
-// (the group loop then runs without branches): when the ring did not yet hold them, the
-// chunk waits for the count and reads the quads again.
+// control snapshot, which the previous chunk then checks (chunk_gate) after its last
+// group, including the snapshot's count of fed T positions (the group loop runs without
+// branches): when the ring did not yet hold them, it waits for the count and reads the
+// quads again.
 // KIND 0: the first 4 R chunks, where rows left of column 0 keep their boundary value;
 // KIND 1: every later chunk.  MASK: KIND 0 chunks select the kept value per cell; without
 // it (floating point, default left boundary, no row padding) a cell left of column 0 is
@@ -371,55 +423,18 @@ __device__ __forceinline__ void compute_chunk(
   __builtin_amdgcn_sched_barrier(0);
   // Per-chunk records are sampled (every CTRACE_EVERY-th chunk): each clock read is a
   // scalar-memory round trip that would otherwise slow the walk being measured.
-  __attribute__((address_space(1))) uint64_t* rec =
-      crec && (k % CTRACE_EVERY) == 0
-          ? (__attribute__((address_space(1))) uint64_t*)(void*)(crec + (int64_t)(k / CTRACE_EVERY) * CTRACE_WORDS)
-          : nullptr;
+  glb_u64* rec = chunk_trace(crec, k);
   if (rec && lane == 0) rec[0] = wall_clock64();
-  // Chunk start: publish progress (and, as the compute wave above the consumer, how far
-  // the consumer's T ring is written: every position of the earlier chunks), then wait
-  // until the c ring holds the next chunk, the H slot is free, the T ring holds this
-  // chunk's positions, and the consumer's T slots for this chunk have been read.
+  const lds_u8* tr_base = L8(L.tring);
   CBAR();
+  // Publish, with one store, that the chunks before this one are done (progress) and that
+  // this chunk's T quads are in registers, so the feeder (or the compute wave above) may
+  // reuse their slots (t_reset); as the compute wave above the consumer, also how far
+  // the consumer's T ring is written: every position of the earlier chunks.
   if (lane == 0) {
-    st_ctl(&L.progress, (uint32_t)pos);
+    *(volatile lds_u2*)L8(&L.progress) = u2{(uint32_t)pos, (uint32_t)(pos + 64 * R + CHUNK)};
     if (CONS == 1) st_ctl(&C->t_fed, (uint32_t)pos);
   }
-  const lds_u8* tr_base = L8(L.tring);
-  {
-    const int need_c = k + 2 < NCc ? k + 2 : NCc;
-    const int need_h = pos + CHUNK - H_SLOTS * CHUNK;
-    const int need_f = pos + 64 * R + CHUNK;
-    const int need_t = pos + CHUNK - RING_T;
-    auto ok = [&](const CtlSnap& v) {
-      return (int)__builtin_amdgcn_readfirstlane(v.own.x) >= need_c &&
-             (int)__builtin_amdgcn_readfirstlane(v.own.y) >= need_h &&
-             (int)__builtin_amdgcn_readfirstlane(v.own.z) >= need_f &&
-             (CONS != 1 || (int)v.cons_t_reset >= need_t);
-    };
-    snap.keep_live();
-    if (!ok(snap)) {
-      const uint64_t c0 = a.trace ? __builtin_readcyclecounter() : 0;
-      if (rec && lane == 0) {
-        rec[3] = ((int)snap.own.x < need_c ? 1u : 0u) | ((int)snap.own.y < need_h ? 2u : 0u) |
-                 ((int)snap.own.z < need_f ? 4u : 0u) | (CONS == 1 && (int)snap.cons_t_reset < need_t ? 8u : 0u);
-      }
-      wait_until<false>([&] { snap_ctl<CONS>(L, C, snap); return ok(snap); }, lds, a);
-      // The chunk's T quads were read before the ring held them all: read them again
-      // (after the snapshot that shows they are there, so they are the fed values).
-      read_t<R>(k, tr_base, tc);
-      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the re-read quads are in registers
-      if (a.trace && lane == 0) L.tr_chunk_wait += __builtin_readcyclecounter() - c0;
-    }
-    if (rec && lane == 0) {
-      rec[1] = wall_clock64();
-      rec[2] = L.tr_t_wait;
-    }
-  }
-  CBAR();
-  // The chunk's T quads are in registers: let the feeder (or the compute wave above)
-  // reuse their slots.
-  if (lane == 0) st_ctl(&L.t_reset, (uint32_t)(pos + 64 * R + CHUNK));
   if (rec && lane == 0) rec[9] = wall_clock64();
   read_c<R>(k + 1, cq, cn);
   const int hb = (k % H_SLOTS) * (R * SLAB);
@@ -492,6 +507,8 @@ __device__ __forceinline__ void compute_chunk(
       ((__attribute__((address_space(1))) uint64_t*)(void*)crec)[(int64_t)(k / CTRACE_EVERY) * CTRACE_WORDS + 10] =
           wall_clock64();
   }
+  // The next chunk's start conditions, on the snapshot read during the last group.
+  if (k + 1 < NCc) chunk_gate<R, CONS>(k + 1, NCc, lds, L, C, snap, tn, a, lane, chunk_trace(crec, k + 1));
 }
 
 template <typename T, int RULE, int R, int CONS, bool MASK>
@@ -527,6 +544,7 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   CtlSnap snap;
   snap_ctl<CONS>(L, C, snap);
   read_t<R>(0, L8(L.tring), tA);  // after the snapshot, as in every chunk
+  chunk_gate<R, CONS>(0, NCc, lds, L, C, snap, tA, a, lane, chunk_trace(crec, 0));
 #define WF_CHUNK(KIND, KK, CUR_C, CUR_T, NXT_C, NXT_T)                                                         \
   compute_chunk<T, RULE, R, KIND, CONS, MASK>(KK, G, gT, NCc, lds, L, C, hand_out, cq, hq, ct_base, lane63, lane,  \
                                         CUR_C, CUR_T, NXT_C, NXT_T, tprev_w, H, Hp, Np, snap, a, crec, hand_local)
