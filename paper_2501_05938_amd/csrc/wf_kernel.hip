@@ -312,10 +312,14 @@ __device__ __forceinline__ void read_c(int kn, const lds_u8* const (&cq)[4], u4 
 }
 template <int R>
 __device__ __forceinline__ void read_t(int kn, const lds_u8* tr_base, u4 (&t)[4]) {
-  // The chunk's 16 positions are contiguous in the ring (it holds a whole number of chunks).
-  const lds_u8* tb = tr_base + ((CHUNK * kn + 64 * R) & (RING_T - 1)) * 4;
+  // The chunk's 16 positions are contiguous in the ring (it holds a whole number of
+  // chunks).  Their address is the same in every lane; held in one vector register, the
+  // four reads take their distance from it as an immediate offset (a scalar address
+  // would be copied into a vector register for each read).
+  uint32_t tb = (uint32_t)(uintptr_t)(tr_base + ((CHUNK * kn + 64 * R) & (RING_T - 1)) * 4);
+  asm volatile("" : "+v"(tb));
 #pragma unroll
-  for (int q = 0; q < 4; ++q) t[q] = lds_ld4_fresh(tb + 16 * q);
+  for (int q = 0; q < 4; ++q) t[q] = lds_ld4_fresh((const lds_u8*)(uintptr_t)tb + 16 * q);
 }
 
 // Control words a chunk start checks, read ahead of time.  The counters only grow, so
@@ -411,12 +415,12 @@ __device__ __forceinline__ void chunk_gate(int k, int NCc, WaveLds* lds, WaveLds
 // nothing stores or reads.
 // CONS: 0 = no consumer, 1 = the next compute wave (LDS), 2 = the next band (global
 // handoff row).
-template <typename T, int RULE, int R, int KIND, int CONS, bool MASK>
+template <typename T, int RULE, int R, int KIND, int CONS, bool MASK, bool LOCAL>
 __device__ __forceinline__ void compute_chunk(
     int k, int G, int gT, int NCc, WaveLds* lds, WaveLds& L, WaveLds* C,
     __amdgpu_buffer_rsrc_t hand_out, const lds_u8* const (&cq)[4], lds_u8* const (&hq)[4], lds_u8* ct_base,
     bool lane63, int lane, const u4 (&cc)[R][4], u4 (&tc)[4], u4 (&cn)[R][4], u4 (&tn)[4], uint32_t& tprev_w,
-    T (&H)[R], T (&Hp)[R], T& Np, CtlSnap& snap, const KArgs& a, uint64_t* crec, bool hand_local) {
+    T (&H)[R], T (&Hp)[R], T& Np, CtlSnap& snap, const KArgs& a, uint64_t* crec) {
   const int pos = CHUNK * k;
   // Keep the chunk-start check (and the scalar copies of the control snapshot it takes)
   // from being scheduled into the previous chunk's walk.
@@ -498,10 +502,8 @@ __device__ __forceinline__ void compute_chunk(
     // the others are never read by a consumer and stay at the sentinel.
     const int g = 4 * k + lane - 60;
     if (lane >= 60 && g < G && (KIND != 0 || g >= 16 * R - 1)) {
-      // A consumer on this XCD polls through the shared L2, which a plain store reaches;
-      // one on another XCD needs the store to go through to memory.
-      if (hand_local) __builtin_amdgcn_raw_buffer_store_b128(hand4, hand_out, 16 * g, 0, 0);
-      else __builtin_amdgcn_raw_buffer_store_b128(hand4, hand_out, 16 * g, 0, CPOL_SC1);
+      // LOCAL: the consumer is on this XCD (plain store through the shared L2).
+      __builtin_amdgcn_raw_buffer_store_b128(hand4, hand_out, 16 * g, 0, LOCAL ? 0 : CPOL_SC1);
     }
     if (crec && (k % CTRACE_EVERY) == 4 && lane == 0)
       ((__attribute__((address_space(1))) uint64_t*)(void*)crec)[(int64_t)(k / CTRACE_EVERY) * CTRACE_WORDS + 10] =
@@ -511,11 +513,11 @@ __device__ __forceinline__ void compute_chunk(
   if (k + 1 < NCc) chunk_gate<R, CONS>(k + 1, NCc, lds, L, C, snap, tn, a, lane, chunk_trace(crec, k + 1));
 }
 
-template <typename T, int RULE, int R, int CONS, bool MASK>
+template <typename T, int RULE, int R, int CONS, bool MASK, bool LOCAL>
 __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLds& L, WaveLds* C,
                                              __amdgpu_buffer_rsrc_t hand_out, const lds_u8* const (&cq)[4],
                                              lds_u8* const (&hq)[4], int lane, const T (&Hinit)[R], const KArgs& a,
-                                             uint64_t* crec, bool hand_local) {
+                                             uint64_t* crec) {
   const int NCc = (4 * G + CHUNK - 1) / CHUNK;
   lds_u8* ct_base = CONS == 1 ? L8(C->tring) : nullptr;
   const bool lane63 = lane == 63;
@@ -546,8 +548,8 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   read_t<R>(0, L8(L.tring), tA);  // after the snapshot, as in every chunk
   chunk_gate<R, CONS>(0, NCc, lds, L, C, snap, tA, a, lane, chunk_trace(crec, 0));
 #define WF_CHUNK(KIND, KK, CUR_C, CUR_T, NXT_C, NXT_T)                                                         \
-  compute_chunk<T, RULE, R, KIND, CONS, MASK>(KK, G, gT, NCc, lds, L, C, hand_out, cq, hq, ct_base, lane63, lane,  \
-                                        CUR_C, CUR_T, NXT_C, NXT_T, tprev_w, H, Hp, Np, snap, a, crec, hand_local)
+  compute_chunk<T, RULE, R, KIND, CONS, MASK, LOCAL>(KK, G, gT, NCc, lds, L, C, hand_out, cq, hq, ct_base, lane63,   \
+                                                    lane, CUR_C, CUR_T, NXT_C, NXT_T, tprev_w, H, Hp, Np, snap, a, crec)
   int k = 0;
   // The first 4 R chunks (groups 0 .. 16 R - 1, where rows left of column 0 are masked;
   // a walk always has at least that many).
@@ -620,21 +622,26 @@ __device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLd
   // no row padding (the inputs read for them are then the finite tail of the row above).
   const bool unmasked = !std::is_integral<T>::value && g.left == nullptr && g.ld_cost == n;
   if (lds_consumer) {
-    compute_walk<T, RULE, R, 1, true>(G, gT, lds, L, &lds[w + 1], __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec,
-                                      false);
+    compute_walk<T, RULE, R, 1, true, false>(G, gT, lds, L, &lds[w + 1], __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a,
+                                             crec);
   } else if (glob_consumer) {
     __amdgpu_buffer_rsrc_t hand_out = make_rsrc(g.hand + (int64_t)band * g.hand_ld, (uint32_t)(g.hand_ld * 4));
-    if (unmasked)
-      compute_walk<T, RULE, R, 2, false>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec, hand_local);
-    else
-      compute_walk<T, RULE, R, 2, true>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec, hand_local);
+    // A consumer on this XCD polls through the shared L2, which a plain store reaches;
+    // one on another XCD needs the handoff stores to go through to memory.
+    if (unmasked) {
+      if (hand_local) compute_walk<T, RULE, R, 2, false, true>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec);
+      else compute_walk<T, RULE, R, 2, false, false>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec);
+    } else {
+      if (hand_local) compute_walk<T, RULE, R, 2, true, true>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec);
+      else compute_walk<T, RULE, R, 2, true, false>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec);
+    }
   } else {
     if (unmasked)
-      compute_walk<T, RULE, R, 0, false>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec,
-                                         false);
+      compute_walk<T, RULE, R, 0, false, false>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a,
+                                                crec);
     else
-      compute_walk<T, RULE, R, 0, true>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a, crec,
-                                        false);
+      compute_walk<T, RULE, R, 0, true, false>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a,
+                                               crec);
   }
   if (a.trace && lane == 0) L.tr_end = __builtin_readcyclecounter();
 }
