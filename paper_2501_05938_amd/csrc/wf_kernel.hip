@@ -147,16 +147,6 @@ template <> struct Num<double> {
   template <int RULE> __device__ static double absent() { return RULE == 0 ? __builtin_inf() : -__builtin_inf(); }
 };
 
-// N for every lane: lane r receives lane r-1's `src`; lane 0 keeps `old`.
-// Shift acc one lane down within each row of 16 lanes (lane i takes lane i+1) and put
-// this lane's h where no source lane exists (lanes 15, 31, 47, 63).  After j calls,
-// lane 63-i holds the h of the (j-i)-th call.
-__device__ __forceinline__ void shift_in_lane63(u4& acc, const u4& h) {
-#pragma unroll
-  for (int e = 0; e < 4; ++e)
-    acc[e] = (uint32_t)__builtin_amdgcn_update_dpp((int)h[e], (int)acc[e], 0x101, 0xf, 0xf, false);
-}
-
 // Four absent boundary values (the T ring's padding past a band's last T position).
 template <typename T, int RULE> __device__ __forceinline__ u4 absent4() {
   const uint32_t v = bits(Num<T>::template absent<RULE>());
@@ -170,6 +160,7 @@ __host__ __device__ constexpr int t_pad_end(int G, int R) { return CHUNK * ((4 *
 // (position p holds the row above at column p - (64 R - 1)).
 __host__ __device__ constexpr int t_first(int R) { return 64 * R - 4; }
 
+// N for every lane: lane r receives lane r-1's `src`; lane 0 keeps `old`.
 template <typename T> __device__ __forceinline__ T dpp_shr1(T old, T src) {
   return from_bits<T>((uint32_t)__builtin_amdgcn_update_dpp((int)bits(old), (int)bits(src), 0x138, 0xf, 0xf, false));
 }
@@ -419,7 +410,8 @@ template <typename T, int RULE, int R, int KIND, int CONS, bool MASK, bool LOCAL
 __device__ __forceinline__ void compute_chunk(
     int k, int G, int gT, int NCc, WaveLds* lds, WaveLds& L, WaveLds* C,
     __amdgpu_buffer_rsrc_t hand_out, const lds_u8* const (&cq)[4], lds_u8* const (&hq)[4], lds_u8* ct_base,
-    bool lane63, int lane, const u4 (&cc)[R][4], u4 (&tc)[4], u4 (&cn)[R][4], u4 (&tn)[4], uint32_t& tprev_w,
+    const lds_u8* hrd, bool lane63, int lane, const u4 (&cc)[R][4], u4 (&tc)[4], u4 (&cn)[R][4], u4 (&tn)[4],
+    uint32_t& tprev_w,
     T (&H)[R], T (&Hp)[R], T& Np, CtlSnap& snap, const KArgs& a, uint64_t* crec) {
   const int pos = CHUNK * k;
   // Keep the chunk-start check (and the scalar copies of the control snapshot it takes)
@@ -443,10 +435,11 @@ __device__ __forceinline__ void compute_chunk(
   read_c<R>(k + 1, cq, cn);
   const int hb = (k % H_SLOTS) * (R * SLAB);
   lds_u8* ct = ct_base + (pos & (RING_T - 1)) * 4;
-  // Bottom-row quads of the chunk for the next band, gathered into lanes 60..63 (lane 63
-  // holds the last group's quad, lane 62 the one before, ...) and stored once at the end
-  // of the chunk.
-  u4 hand4 = {0u, 0u, 0u, 0u};
+  // Bottom-row quads of the chunk for the next band, stored once at the end of the chunk
+  // from lanes 60..63 (lane 60 + q: group q's quad).  Lane 63 computes them; lanes 60..62
+  // read groups 0..2's from the H ring (hrd: lane 63's quad lane - 60 of slot 0) while
+  // group 3 runs, and lane 63 keeps group 3's own.
+  u4 hv = {0u, 0u, 0u, 0u}, h4_last = {0u, 0u, 0u, 0u};
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int g = 4 * k + q;
@@ -456,6 +449,10 @@ __device__ __forceinline__ void compute_chunk(
     if (q == 3) {
       snap_ctl<CONS>(L, C, snap);
       read_t<R>(k + 1, tr_base, tn);
+      if (CONS == 2) {
+        asm volatile("" ::: "memory");  // after groups 0..2's H ring writes
+        hv = lds_ld4(hrd + hb);
+      }
     }
     const u4 tv = tc[q];
     const uint32_t tk[4] = {tprev_w, tv.x, tv.y, tv.z};
@@ -488,19 +485,17 @@ __device__ __forceinline__ void compute_chunk(
     // read by a consumer.
 #pragma unroll
     for (int sr = 0; sr < R; ++sr) lds_st4(hq[q] + hb + sr * SLAB, h4[sr]);
+    if (q == 3) h4_last = h4[R - 1];
     if (CONS == 1 && (KIND != 0 || g >= 16 * R - 1)) {
       // Past the last group the consumer's ring gets absent values (its padding).
       if (lane63) lds_st4(ct + 16 * q, g < G ? h4[R - 1] : absent4<T, RULE>());
-    }
-    if (CONS == 2) {
-      if (q == 0) hand4 = h4[R - 1];  // lane 63 holds group 0's quad; the other lanes' values are shifted out
-      else shift_in_lane63(hand4, h4[R - 1]);
     }
   }
   if (CONS == 2) {
     // Lane 60+q holds group 4k+q's quad.  Only positions [t_first(R), 4G) are written:
     // the others are never read by a consumer and stay at the sentinel.
     const int g = 4 * k + lane - 60;
+    const u4 hand4 = lane63 ? h4_last : hv;
     if (lane >= 60 && g < G && (KIND != 0 || g >= 16 * R - 1)) {
       // LOCAL: the consumer is on this XCD (plain store through the shared L2).
       __builtin_amdgcn_raw_buffer_store_b128(hand4, hand_out, 16 * g, 0, LOCAL ? 0 : CPOL_SC1);
@@ -516,8 +511,8 @@ __device__ __forceinline__ void compute_chunk(
 template <typename T, int RULE, int R, int CONS, bool MASK, bool LOCAL>
 __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLds& L, WaveLds* C,
                                              __amdgpu_buffer_rsrc_t hand_out, const lds_u8* const (&cq)[4],
-                                             lds_u8* const (&hq)[4], int lane, const T (&Hinit)[R], const KArgs& a,
-                                             uint64_t* crec) {
+                                             lds_u8* const (&hq)[4], const lds_u8* hrd, int lane, const T (&Hinit)[R],
+                                             const KArgs& a, uint64_t* crec) {
   const int NCc = (4 * G + CHUNK - 1) / CHUNK;
   lds_u8* ct_base = CONS == 1 ? L8(C->tring) : nullptr;
   const bool lane63 = lane == 63;
@@ -548,8 +543,9 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   read_t<R>(0, L8(L.tring), tA);  // after the snapshot, as in every chunk
   chunk_gate<R, CONS>(0, NCc, lds, L, C, snap, tA, a, lane, chunk_trace(crec, 0));
 #define WF_CHUNK(KIND, KK, CUR_C, CUR_T, NXT_C, NXT_T)                                                         \
-  compute_chunk<T, RULE, R, KIND, CONS, MASK, LOCAL>(KK, G, gT, NCc, lds, L, C, hand_out, cq, hq, ct_base, lane63,   \
-                                                    lane, CUR_C, CUR_T, NXT_C, NXT_T, tprev_w, H, Hp, Np, snap, a, crec)
+  compute_chunk<T, RULE, R, KIND, CONS, MASK, LOCAL>(KK, G, gT, NCc, lds, L, C, hand_out, cq, hq, ct_base, hrd,      \
+                                                    lane63, lane, CUR_C, CUR_T, NXT_C, NXT_T, tprev_w, H, Hp, Np, snap, \
+                                                    a, crec)
   int k = 0;
   // The first 4 R chunks (groups 0 .. 16 R - 1, where rows left of column 0 are masked;
   // a walk always has at least that many).
@@ -617,30 +613,32 @@ __device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLd
     cq[q] = L8(rings[w].cring) + quad_off(lane, q);
     hq[q] = L8(rings[w].hring) + quad_off(lane, q);
   }
+  // Lanes 60..62: the bottom row's quad lane - 60 in H ring slot 0 (the handoff gather).
+  const lds_u8* hrd = L8(rings[w].hring) + quad_off(63, lane >= 60 && lane < 63 ? lane - 60 : 0) + (R - 1) * SLAB;
   // Cells left of column 0 need no per-cell selection when they stay at the absent
   // value by themselves (see compute_chunk): floating point, default left boundary, and
   // no row padding (the inputs read for them are then the finite tail of the row above).
   const bool unmasked = !std::is_integral<T>::value && g.left == nullptr && g.ld_cost == n;
   if (lds_consumer) {
-    compute_walk<T, RULE, R, 1, true, false>(G, gT, lds, L, &lds[w + 1], __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a,
+    compute_walk<T, RULE, R, 1, true, false>(G, gT, lds, L, &lds[w + 1], __amdgpu_buffer_rsrc_t(), cq, hq, hrd, lane, H, a,
                                              crec);
   } else if (glob_consumer) {
     __amdgpu_buffer_rsrc_t hand_out = make_rsrc(g.hand + (int64_t)band * g.hand_ld, (uint32_t)(g.hand_ld * 4));
     // A consumer on this XCD polls through the shared L2, which a plain store reaches;
     // one on another XCD needs the handoff stores to go through to memory.
     if (unmasked) {
-      if (hand_local) compute_walk<T, RULE, R, 2, false, true>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec);
-      else compute_walk<T, RULE, R, 2, false, false>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec);
+      if (hand_local) compute_walk<T, RULE, R, 2, false, true>(G, gT, lds, L, nullptr, hand_out, cq, hq, hrd, lane, H, a, crec);
+      else compute_walk<T, RULE, R, 2, false, false>(G, gT, lds, L, nullptr, hand_out, cq, hq, hrd, lane, H, a, crec);
     } else {
-      if (hand_local) compute_walk<T, RULE, R, 2, true, true>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec);
-      else compute_walk<T, RULE, R, 2, true, false>(G, gT, lds, L, nullptr, hand_out, cq, hq, lane, H, a, crec);
+      if (hand_local) compute_walk<T, RULE, R, 2, true, true>(G, gT, lds, L, nullptr, hand_out, cq, hq, hrd, lane, H, a, crec);
+      else compute_walk<T, RULE, R, 2, true, false>(G, gT, lds, L, nullptr, hand_out, cq, hq, hrd, lane, H, a, crec);
     }
   } else {
     if (unmasked)
-      compute_walk<T, RULE, R, 0, false, false>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a,
+      compute_walk<T, RULE, R, 0, false, false>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, hrd, lane, H, a,
                                                 crec);
     else
-      compute_walk<T, RULE, R, 0, true, false>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, lane, H, a,
+      compute_walk<T, RULE, R, 0, true, false>(G, gT, lds, L, nullptr, __amdgpu_buffer_rsrc_t(), cq, hq, hrd, lane, H, a,
                                                crec);
   }
   if (a.trace && lane == 0) L.tr_end = __builtin_readcyclecounter();
