@@ -1185,9 +1185,15 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
   const __amdgpu_buffer_rsrc_t hand_in = make_rsrc(g.hand + (int64_t)(band - 1) * g.hand_ld, (uint32_t)(g.hand_ld * 4));
   int want = SMALL;
   // Poll: quads [base, base + 4 nq) of the handoff row (nq = 0: nothing issued).
+  // How far the ring has room (t_reset + RING_T, at most t_pad), re-read from LDS only when
+  // a poll would reach past the last value read: the ring is rarely that full, and a
+  // poll issued behind an LDS read waits for it.
+  int limit = t_first(R) + RING_T < t_pad ? t_first(R) + RING_T : t_pad;
   auto issue = [&](u4& v, int& base, int& nq) {
-    int limit = (int)ld_ctl(&L.t_reset) + RING_T;
-    if (limit > t_pad) limit = t_pad;
+    if (tw + 4 * want > limit && limit < t_pad) {
+      limit = (int)ld_ctl(&L.t_reset) + RING_T;
+      if (limit > t_pad) limit = t_pad;
+    }
     base = tw;
     nq = (limit - tw) / 4;
     if (nq > want) nq = want;
@@ -1221,7 +1227,8 @@ __device__ __forceinline__ void feeder_band(const GridDesc& g, int band, WaveLds
     tw += 4 * nvalid;
     note_fed();
     want = nvalid == nq - off ? 64 : SMALL;
-    __builtin_amdgcn_s_waitcnt(0xc07f);
+    // LDS accesses of one wave complete in order: a wave that sees the new count reads
+    // the quads written before it.
     CBAR();
     if (lane == 0) st_ctl(&L.t_fed, (uint32_t)tw);
     return nvalid;
