@@ -473,12 +473,13 @@ def serving(torch, wf, wfgen, grids, requests, warmup, load, inflight=4, batch=2
                 outstanding[tk] = (i, g, t_start + arrivals[i])
                 i += 1
             progressed = False
-            for tk in list(outstanding)[:64]:
-                r = srv.poll(tk) if (every and (outstanding[tk][0] - warmup) % every == 0
-                                     and outstanding[tk][0] >= warmup) else srv.poll_times(tk)
-                if r is None:
+            # one call lists the requests finished since the last look
+            for tk in srv.done():
+                if tk not in outstanding:
                     continue
                 t_obs = time.perf_counter()
+                r = srv.poll(tk) if (every and (outstanding[tk][0] - warmup) % every == 0
+                                     and outstanding[tk][0] >= warmup) else srv.poll_times(tk)
                 q, g, t_arr = outstanding.pop(tk)
                 if isinstance(r, dict):
                     sampled[q] = (g, r["out"].clone())

@@ -282,6 +282,13 @@ wf_status wf_release(wf_server* s, uint64_t ticket);
 wf_status wf_server_destroy(wf_server* s);
 /* Bytes of device memory currently held for requests, and the peak so far. */
 wf_status wf_server_memory(wf_server* s, int64_t* in_use, int64_t* peak);
+/* Tickets whose requests have finished (done or failed) since the last call, oldest
+ * first: up to `cap` are written to tickets[0..cap) and their number to *count.  Each
+ * finished ticket is reported once (a ticket released before it is reported is
+ * skipped); wf_poll still returns its result until it is released.  One call replaces
+ * a wf_poll per pending ticket for a caller with many requests in flight.
+ * WF_EINVAL: NULL server or count, cap < 0, or NULL tickets with cap > 0. */
+wf_status wf_server_done(wf_server* s, uint64_t* tickets, int64_t cap, int64_t* count);
 
 /* Latency of one step of the walk's dependency chain on this device, in ns: one wave
  * runs `steps` (16 .. 2^30) steps of N = the neighbour lane's H, H = c + min(N, NW, H)

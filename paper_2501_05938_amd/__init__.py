@@ -115,6 +115,8 @@ _SIGS = {
     "wf_release": (ctypes.c_int, [_P, ctypes.c_uint64]),
     "wf_server_destroy": (ctypes.c_int, [_P]),
     "wf_server_memory": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "wf_server_done": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_int64)]),
     "wf_stream_model_fit": (ctypes.c_int, [ctypes.POINTER(StreamSample), ctypes.c_int64, ctypes.c_double,
                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(StreamModel),
@@ -438,6 +440,8 @@ class Server:
         self._h = _P()
         _check(lib.wf_server_create(context(device) if ctx is None else ctx, ctypes.byref(o), ctypes.byref(self._h)))
         self._keep = {}
+        self._events = {}  # submitting stream -> the event its device inputs' readiness is recorded in
+        self._done_buf = (ctypes.c_uint64 * 4096)()
 
     def _submit(self, r, keep):
         t = ctypes.c_uint64()
@@ -458,8 +462,13 @@ class Server:
             m, n = cost.shape
             r.dtype = DTYPES[_dtype_of(cost)]
             r.input_kind, r.input, r.ld_input = INPUT_DEVICE, cost.data_ptr(), _ld(cost, n)
-            ev = torch.cuda.Event()
-            ev.record(torch.cuda.current_stream(cost.device))
+            # One event per submitting stream, recorded again at every submit: the server's
+            # wait then covers at least the work queued before this submit.
+            stream = torch.cuda.current_stream(cost.device)
+            ev = self._events.get(stream.cuda_stream)
+            if ev is None:
+                ev = self._events[stream.cuda_stream] = torch.cuda.Event()
+            ev.record(stream)
             r.ready_event = ev.cuda_event
         elif isinstance(cost, torch.Tensor) and cost.is_pinned():
             m, n = cost.shape
@@ -518,6 +527,16 @@ class Server:
             return None
         _check(st)
         return res.t_submit, res.t_admit, res.t_launch, res.t_done
+
+    def done(self):
+        """Tickets finished (done or failed) since the last call, oldest first."""
+        out = []
+        n = ctypes.c_int64()
+        while True:
+            _check(load_library().wf_server_done(self._h, self._done_buf, len(self._done_buf), ctypes.byref(n)))
+            out.extend(self._done_buf[:n.value])
+            if n.value < len(self._done_buf):
+                return out
 
     def release(self, ticket: int):
         _check(load_library().wf_release(self._h, ticket))

@@ -99,6 +99,8 @@ __host__ __device__ inline int64_t hand_ld_for(int64_t n, int R) { return ((4 * 
 // R rows per lane: (W, R) = (1, 1), (2, 1) or (1, 2); f64 only (1, 1).
 hipError_t launch_sweep(int dtype, int rule, int W, int R, int nwg, const KArgs& args, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t stream);
+// Arm the handoff rows of grids[0..ngrids) (device descriptor table) with `sent`, in one launch.
+hipError_t launch_arm_hand(const GridDesc* grids, int ngrids, uint32_t sent, hipStream_t stream);
 // Traceback of a computed grid (see wf_traceback): dtype 0 = f32, 1 = i32, 2 = f64.
 hipError_t launch_traceback(int dtype, int rule, const void* H, int64_t ld, int64_t m, int64_t n, const void* top,
                             const void* left, int32_t* path, int64_t* length, hipStream_t stream);

@@ -1384,6 +1384,17 @@ __global__ void xcc_probe_kernel(uint32_t* out) {
   if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
 }
 
+// Arm the handoff rows of every grid of a launch's descriptor table with the sentinel:
+// grid g's (nbands - 1) rows of hand_ld words (blockIdx.y strides over the grids).
+__global__ void arm_hand_kernel(const GridDesc* grids, int ngrids, uint32_t sent) {
+  for (int gi = blockIdx.y; gi < ngrids; gi += gridDim.y) {
+    uint32_t* hand = grids[gi].hand;
+    const int64_t count = (int64_t)(grids[gi].nbands - 1) * grids[gi].hand_ld;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) hand[i] = sent;
+  }
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
@@ -2044,6 +2055,13 @@ hipError_t launch_traceback(int dtype, int rule, const void* H, int64_t ld, int6
 hipError_t launch_xcc_probe(uint32_t* out, int nwg, hipStream_t stream) {
   if (nwg <= 0) return hipSuccess;
   hipLaunchKernelGGL(xcc_probe_kernel, dim3((unsigned)nwg), dim3(64), 0, stream, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_arm_hand(const GridDesc* grids, int ngrids, uint32_t sent, hipStream_t stream) {
+  if (ngrids <= 0) return hipSuccess;
+  const dim3 grid(16, (unsigned)(ngrids < 1024 ? ngrids : 1024));
+  hipLaunchKernelGGL(arm_hand_kernel, grid, dim3(256), 0, stream, grids, ngrids, sent);
   return hipGetLastError();
 }
 

@@ -250,6 +250,7 @@ struct wf_server {
   std::unordered_map<uint64_t, Req> reqs;
   std::deque<uint64_t> queue;     // submitted, not admitted (arrival order)
   std::deque<uint64_t> admitted;  // admitted, not launched
+  std::deque<uint64_t> finished;  // done or failed, not yet reported by wf_server_done
   int inflight = 0;
   uint64_t epoch = 0;             // bumped by every submit, release and stop
   std::string thread_error;       // a HIP failure inside the server thread
@@ -283,6 +284,7 @@ void wf_server::retire(LaunchSlot& L, double t, hipError_t q) {
     } else {
       r.state = DONE;
     }
+    finished.push_back(tk);
   }
   L.tickets.clear();
   L.busy = false;
@@ -378,6 +380,7 @@ bool wf_server::try_admit(Req& q, uint64_t ticket, double t) {
       q.err = st == WF_EHIP && event_pool.empty() && !c.ev ? WF_ENOMEM : st;
       q.msg = wf_last_error();
       q.t_done = t;
+      finished.push_back(ticket);
       if (c.ev) event_pool.push_back(c.ev);
       if (q.r.input_kind == WF_INPUT_HOST) staging.release(c.stage_off, stage_bytes);
       return true;
@@ -439,7 +442,6 @@ wf_status wf_server::enqueue(LaunchSlot& L, std::vector<Req*>& batch, int bs, in
     } else if (q->r.ready_event) {
       WF_HIP(hipStreamWaitEvent(s, (hipEvent_t)q->r.ready_event, 0));
     }
-    if (q->hand_n) WF_HIP(launch_fill_u32(q->hand, sent, (int64_t)q->hand_n, s));
   }
   // Descriptors, largest grid first, and the grid-major work list.
   std::sort(batch.begin(), batch.end(), [](const Req* a, const Req* b) { return a->r.m * a->r.n > b->r.m * b->r.n; });
@@ -473,6 +475,8 @@ wf_status wf_server::enqueue(LaunchSlot& L, std::vector<Req*>& batch, int bs, in
   }
   WF_HIP(hipMemcpyAsync(L.d_grids, L.h_grids, batch.size() * sizeof(GridDesc), hipMemcpyHostToDevice, s));
   WF_HIP(hipMemcpyAsync(L.d_items, L.h_items, nitems * sizeof(Item), hipMemcpyHostToDevice, s));
+  // Every request's handoff rows (arena memory, so of unknown contents) armed in one launch.
+  WF_HIP(launch_arm_hand(L.d_grids, (int)batch.size(), sent, s));
   KArgs a = base_args(ctx, L.ctl, (int64_t)nitems);
   a.grids = L.d_grids;
   a.items = L.d_items;
@@ -530,6 +534,7 @@ bool wf_server::launch_one(std::unique_lock<std::mutex>& lk) {
       q.err = st;
       q.msg = msg;
       q.t_done = now_s();
+      finished.push_back(tk);
     }
     // Nothing may still run on the stream before the slot is reused.
     hipStreamSynchronize(L->stream);
@@ -717,6 +722,20 @@ extern "C" wf_status wf_release(wf_server* s, uint64_t ticket) {
   s->reqs.erase(it);
   ++s->epoch;
   s->cv.notify_one();  // memory freed: admission may proceed
+  return WF_OK;
+}
+
+extern "C" wf_status wf_server_done(wf_server* s, uint64_t* tickets, int64_t cap, int64_t* count) {
+  if (!s || !count) return fail(WF_EINVAL, "server and count must not be NULL");
+  if (cap < 0 || (cap > 0 && !tickets)) return fail(WF_EINVAL, "tickets is NULL or cap < 0");
+  std::lock_guard<std::mutex> g(s->mu);
+  int64_t k = 0;
+  while (k < cap && !s->finished.empty()) {
+    const uint64_t tk = s->finished.front();
+    s->finished.pop_front();
+    if (s->reqs.count(tk)) tickets[k++] = tk;  // (released already through wf_poll: skipped)
+  }
+  *count = k;
   return WF_OK;
 }
 

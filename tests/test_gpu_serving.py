@@ -206,3 +206,33 @@ def test_oversized_and_invalid_requests():
         r = srv.poll(t)
         assert r is not None and r["out"] is None
         srv.release(t)
+
+
+def test_done_reports_each_finished_ticket_once():
+    """wf_server_done lists every finished ticket exactly once, and only finished ones
+    (wf_poll already has its result); results match the grids swept alone."""
+    grids = []
+    for q in range(40):
+        m, n = 64 + 37 * q, 80 + 29 * q
+        c = torch.empty((m, n), dtype=torch.float32, device=DEV)
+        wfgen.fill_device(c, seed=900 + q)
+        grids.append(c)
+    _sync()
+    with wf.Server(budget_bytes=8 << 30) as srv:
+        tickets = [srv.submit(c) for c in grids]
+        seen = []
+        t0 = time.time()
+        while len(seen) < len(tickets):
+            for tk in srv.done():
+                assert srv.poll_times(tk) is not None, "reported before it finished"
+                seen.append(tk)
+            if time.time() - t0 > 60.0:
+                raise TimeoutError(f"{len(tickets) - len(seen)} requests never reported")
+            time.sleep(0.0005)
+        assert sorted(seen) == sorted(tickets) and len(set(seen)) == len(seen)
+        assert srv.done() == []
+        for tk, c in zip(tickets, grids):
+            got = srv.poll(tk)["out"].clone()
+            _sync()
+            assert torch.equal(got, wf.solve(c))
+            srv.release(tk)
