@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--serve-load", type=float, default=0.7)
-    ap.add_argument("--serve-inflight", type=int, default=4, help="server launches in flight")
+    ap.add_argument("--serve-inflight", type=int, default=2, help="server launches in flight")
     ap.add_argument("--serve-batch", type=int, default=256, help="server requests per launch at most")
     ap.add_argument("--copy-ref", action="store_true",
                     help="run one plain 1 GiB device-to-device copy first: a kernel of known HBM "
@@ -426,7 +426,7 @@ def batched(torch, wf, wfgen, count, with_model=True):
     return res
 
 
-def serving(torch, wf, wfgen, grids, requests, warmup, load, inflight=4, batch=256, check=True):
+def serving(torch, wf, wfgen, grids, requests, warmup, load, inflight=2, batch=256, check=True):
     """Poisson arrivals of square grids (n log-uniform in [128, 8192]) served under a
     64 GiB budget with continuous batching.  The arrival rate is `load` times the
     batched capacity for the same mix, measured first with one wf_solve_batched

@@ -224,7 +224,9 @@ typedef struct wf_server wf_server;
 
 typedef struct wf_server_opts {
   int64_t hbm_budget_bytes;  /* bytes of device memory the server may hold for requests (0 = 64 GiB) */
-  int32_t max_inflight;      /* launches allowed in flight at once (0 = 4), each on its own stream */
+  int32_t max_inflight;      /* launches allowed in flight at once (0 = 2), each on its own stream.  More
+                                overlap host set-up with running launches, but persistent launches that
+                                run together share compute units, which slows both: two measured best */
   int32_t max_batch;         /* requests per launch at most (0 = 256) */
   int32_t copy_streams;      /* streams that copy host inputs at admission, overlapping earlier launches
                                 (0 = copy on the launch stream just before the launch; at most 8) */

@@ -588,7 +588,7 @@ extern "C" wf_status wf_server_create(wf_ctx* ctx, const wf_server_opts* opts, w
       o.staging_bytes < 0 || o.max_wait_skip_us < 0)
     return fail(WF_EINVAL, "negative option");
   if (o.hbm_budget_bytes == 0) o.hbm_budget_bytes = (int64_t)64 << 30;
-  if (o.max_inflight == 0) o.max_inflight = 4;
+  if (o.max_inflight == 0) o.max_inflight = 2;
   if (o.max_batch == 0) o.max_batch = 256;
   if (o.staging_bytes == 0) o.staging_bytes = (int64_t)256 << 20;
   if (o.max_wait_skip_us == 0) o.max_wait_skip_us = 20000;
