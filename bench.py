@@ -574,8 +574,8 @@ def copy_serving(torch, wf, wfgen, count=256, batch=16):
                 tks = [srv.submit(h) for h in hosts]
                 pending = set(tks)
                 while pending:
-                    for tk in list(pending):
-                        if srv.poll_times(tk) is not None:
+                    for tk in srv.done():
+                        if tk in pending and srv.poll_times(tk) is not None:
                             pending.discard(tk)
                             srv.release(tk)
                     time.sleep(2e-5)

@@ -196,6 +196,7 @@ struct Copy {
   size_t stage_off, stage_bytes;
   bool staged;
   uint64_t ticket;
+  int stream;  // index into copy_streams
 };
 
 template <class T>
@@ -292,27 +293,35 @@ void wf_server::retire(LaunchSlot& L, double t, hipError_t q) {
 }
 
 void wf_server::reap_copies() {
-  for (size_t i = 0; i < copying.size();) {
-    if (hipEventQuery(copying[i].ev) == hipErrorNotReady) {
-      ++i;
+  // `copying` is in issue order and the copies of one stream complete in order, so only
+  // each stream's oldest pending copy is queried (hundreds may be pending at once).
+  uint32_t busy = 0;  // bit s: copy stream s has a copy still in flight
+  size_t w = 0;
+  for (size_t i = 0; i < copying.size(); ++i) {
+    const Copy c = copying[i];
+    const uint32_t bit = 1u << c.stream;
+    if ((busy & bit) || hipEventQuery(c.ev) == hipErrorNotReady) {
+      busy |= bit;
+      copying[w++] = c;
       continue;
     }
-    if (copying[i].staged) staging.release(copying[i].stage_off, copying[i].stage_bytes);
+    if (c.staged) staging.release(c.stage_off, c.stage_bytes);
     // The copy has landed: a launch not enqueued yet need not wait for it (the event
     // goes back to the pool and may be recorded again for another copy).
-    auto it = reqs.find(copying[i].ticket);
-    if (it != reqs.end() && it->second.copied == copying[i].ev) it->second.copied = nullptr;
-    event_pool.push_back(copying[i].ev);
-    copying[i] = copying.back();
-    copying.pop_back();
+    auto it = reqs.find(c.ticket);
+    if (it != reqs.end() && it->second.copied == c.ev) it->second.copied = nullptr;
+    event_pool.push_back(c.ev);
   }
+  copying.resize(w);
 }
 
 // Copy a host input to its device block on the next copy stream (pageable inputs go
 // through pinned staging first; pinned ones are copied directly).
 wf_status wf_server::start_copy(Req& q, Copy* c) {
   const size_t row = (size_t)q.r.n * 4, bytes = row * (size_t)q.r.m;
-  hipStream_t cs = copy_streams[next_copy++ % copy_streams.size()];
+  const size_t si = next_copy++ % copy_streams.size();
+  hipStream_t cs = copy_streams[si];
+  c->stream = (int)si;
   c->staged = false;
   const char* src = (const char*)q.r.input;
   const bool dense = q.r.ld_input == q.r.n;
