@@ -645,6 +645,9 @@ __device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLd
 }
 
 // ------------------------------------------------------------- IO waves
+#ifndef WF_LOADER_DMA
+#define WF_LOADER_DMA 0
+#endif
 // The staging work of compute wave w is split over waves that never mix load
 // and store traffic: on gfx9 the vector-memory counter does not return loads
 // and stores in order with respect to each other, so a wave holding both must
@@ -863,6 +866,60 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
   int issued = 0, committed = 0;
   Watch t_idle;
   uint32_t polls = 0;
+#if !WF_LOADER_DMA
+  // Clean chunks go through registers: LOAD_DEPTH chunks' loads in flight, each chunk
+  // written into its c slot with ordinary LDS stores once it has landed and the slot
+  // is free.  (Loads that write LDS directly, buffer_load ... lds, take the LDS away
+  // from the compute wave whenever their data arrives; ordinary stores are arbitrated
+  // like any wave's, and the compute wave's raised priority wins.)  The loop is straight
+  // line, so the compiler's waits for the loads count exactly the younger ones: loads
+  // past the clean chunks are issued at an out-of-range offset (they read zeros and are
+  // never used) rather than skipped.
+  if (k_clean > 0) {
+    constexpr int LOAD_DEPTH = 4;
+    u4 buf[LOAD_DEPTH][R][4];
+    auto issue = [&](int k, u4 (&b)[R][4]) {
+      const bool in = k < k_clean;
+#pragma unroll
+      for (int s = 0; s < R; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          b[s][i] = __builtin_amdgcn_raw_buffer_load_b128(rsrc, in ? voff0[s][i] + 64u * (uint32_t)k : 0xFFFFFFFFu, 0, 0);
+    };
+#pragma unroll
+    for (int j = 0; j < LOAD_DEPTH; ++j) issue(j, buf[j]);
+    bool ok = true;
+    for (int k0 = 0; k0 < k_clean && ok; k0 += LOAD_DEPTH) {
+#pragma unroll
+      for (int j = 0; j < LOAD_DEPTH; ++j) {
+        const int k = k0 + j;
+        // The slot last held chunk k - C_SLOTS: wait until the compute wave is past it.
+        if (ok && k < k_clean && (int)ld_ctl(&L.progress) < 16 * (k - C_SLOTS + 1)) {
+          const uint64_t c0 = a.trace ? __builtin_readcyclecounter() : 0;
+          while ((int)ld_ctl(&L.progress) < 16 * (k - C_SLOTS + 1))
+            if (!(ok = io_idle<false>(lds, a, t_idle, polls))) break;
+          if (a.trace && lane == 0) L.tr_load_wait += __builtin_readcyclecounter() - c0;
+        }
+        if (ok && k < k_clean) {
+          t_idle.reset();
+          lds_u8* slot = L8(cring) + (k % C_SLOTS) * (R * SLAB);
+#pragma unroll
+          for (int s = 0; s < R; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) lds_st4(slot + SLAB * s + 1024 * i + 16 * lane, buf[j][s][i]);
+          // LDS accesses of one wave complete in order: a wave that sees the new count
+          // reads the chunk written before it.
+          CBAR();
+          if (lane == 0) st_ctl(&L.c_ready, (uint32_t)(k + 1));
+        }
+        issue(k + LOAD_DEPTH, buf[j]);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): the DMA path below counts only its own loads
+    if (!ok) return;
+    issued = committed = k_clean;
+  }
+#endif
   for (;;) {
     // Issue every chunk whose slot the compute wave has released: slot k % C_SLOTS
     // last held chunk k - C_SLOTS, read completely once progress >= 16 (k - C_SLOTS + 1).
