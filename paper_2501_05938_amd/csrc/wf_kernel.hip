@@ -645,9 +645,6 @@ __device__ __forceinline__ void compute_band(const GridDesc& g, int band, WaveLd
 }
 
 // ------------------------------------------------------------- IO waves
-#ifndef WF_LOADER_DMA
-#define WF_LOADER_DMA 0
-#endif
 // The staging work of compute wave w is split over waves that never mix load
 // and store traffic: on gfx9 the vector-memory counter does not return loads
 // and stores in order with respect to each other, so a wave holding both must
@@ -866,7 +863,6 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
   int issued = 0, committed = 0;
   Watch t_idle;
   uint32_t polls = 0;
-#if !WF_LOADER_DMA
   // Clean chunks go through registers: LOAD_DEPTH chunks' loads in flight, each chunk
   // written into its c slot with ordinary LDS stores once it has landed and the slot
   // is free.  (Loads that write LDS directly, buffer_load ... lds, take the LDS away
@@ -919,7 +915,8 @@ __device__ __forceinline__ void loader_band(const GridDesc& g, int band, WaveLds
     if (!ok) return;
     issued = committed = k_clean;
   }
-#endif
+  // The remaining chunks (those holding the grid's end) are loaded straight into the c
+  // ring (buffer_load ... lds), with the fix-ups below.
   for (;;) {
     // Issue every chunk whose slot the compute wave has released: slot k % C_SLOTS
     // last held chunk k - C_SLOTS, read completely once progress >= 16 (k - C_SLOTS + 1).
