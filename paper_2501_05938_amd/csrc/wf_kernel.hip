@@ -757,11 +757,11 @@ __device__ __forceinline__ bool io_idle(WL* lds, const KArgs& a, Watch& w, uint3
 __device__ __forceinline__ int io_quad(int lane) { return (lane & 3) ^ ((lane >> 3) & 3); }
 
 // Loader of a dynamic-time-warping band (GridDesc::kind 1, fp32): the inputs of chunk
-// k are computed rather than loaded.  Lane L covers the same (row, quad) cells as in
-// the DMA path and writes |x[row] - y[col]| for its four columns into the same slot
-// position; x[row] stays in registers for the whole band, and y is read at the column
-// clamped into [0, n), the value of a column outside the grid then replaced by 0 (those
-// cells are never used).  Only the m + n sequence values are read from memory.
+// k are computed rather than loaded.  Lane L covers the same (row, quad) cells as the
+// grid loader and writes |x[row] - y[col]| for its four columns into the same slot
+// position; x[row] stays in registers for the whole band, and a column outside [0, n)
+// reads y as 0 (those cells are never used).  Only the m + n sequence values are read
+// from memory.
 template <int W, int R>
 __device__ __forceinline__ void absdiff_loader_band(const GridDesc& g, const BandGeom& B, WaveLds& L,
                                                     unsigned char* cring, WaveLds* lds, int lane, const KArgs& a) {
@@ -779,32 +779,91 @@ __device__ __forceinline__ void absdiff_loader_band(const GridDesc& g, const Ban
   const __attribute__((address_space(1))) float* ys = GC<float>(g.sy);
   Watch t_idle;
   uint32_t polls = 0;
-  for (int k = 0; k < B.NC; ++k) {
-    // The slot last held chunk k - C_SLOTS: wait until the compute wave is past it.
-    while ((int)ld_ctl(&L.progress) < 16 * (k - C_SLOTS + 1))
-      if (!io_idle<false>(lds, a, t_idle, polls)) return;
-    t_idle.reset();
+  bool ok = true;
+  // The slot last held chunk k - C_SLOTS: wait until the compute wave is past it.
+  auto slot_free = [&](int k) {
+    while (ok && (int)ld_ctl(&L.progress) < 16 * (k - C_SLOTS + 1))
+      ok = io_idle<false>(lds, a, t_idle, polls);
+    if (ok) t_idle.reset();
+    return ok;
+  };
+  auto write_slot = [&](int k, const u4 (&yq)[R][4]) {
     lds_u8* slot = L8(cring) + (k % C_SLOTS) * (R * SLAB);
 #pragma unroll
     for (int s = 0; s < R; ++s)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
+        const u4 y = yq[s][i];
+        const uint32_t yv[4] = {y.x, y.y, y.z, y.w};
+        uint32_t dv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float d = xv[s][i] - __builtin_bit_cast(float, yv[e]);  // one fp32 rounding
+          dv[e] = bits(__builtin_fabsf(d));                              // exact
+        }
+        lds_st4(slot + SLAB * s + 1024 * i + 16 * lane, u4{dv[0], dv[1], dv[2], dv[3]});
+      }
+    // LDS accesses of one wave complete in order: a wave that sees the new count reads
+    // the chunk written before it.
+    CBAR();
+    if (lane == 0) st_ctl(&L.c_ready, (uint32_t)(k + 1));
+  };
+  // Chunks with a quad reaching left of column 0 or right of column n - 1: element loads,
+  // columns outside [0, n) read as 0 (those cells are never used).
+  auto edge_chunk = [&](int k) {
+    if (!slot_free(k)) return;
+    u4 yq[R][4];
+#pragma unroll
+    for (int s = 0; s < R; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
         const int col = 16 * k + 4 * lq - rho[s][i];
-        u4 v;
+        uint32_t y4[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int cc = col + e;
           const bool in = cc >= 0 && cc < B.n;
-          const float y = in ? ys[in ? cc : 0] : 0.0f;
-          const float d = xv[s][i] - y;  // one fp32 rounding; the absolute value is exact
-          v[e] = bits(__builtin_fabsf(d));
+          y4[e] = in ? bits(ys[in ? cc : 0]) : 0u;
         }
-        lds_st4(slot + SLAB * s + 1024 * i + 16 * lane, v);
+        yq[s][i] = u4{y4[0], y4[1], y4[2], y4[3]};
       }
-    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the slot is written before it is published
-    CBAR();
-    if (lane == 0) st_ctl(&L.c_ready, (uint32_t)(k + 1));
+    write_slot(k, yq);
+  };
+  // Chunks [k_lo, k_hi) have every lane's quads inside [0, n): 16-byte loads through
+  // registers, LOAD_DEPTH chunks in flight, in a straight-line loop (so the compiler's
+  // waits count exactly the younger loads; loads past k_hi use an out-of-range offset,
+  // read zeros and are never used).
+  const int k_lo = (64 * R - 1 + 15) / 16;
+  const int k_hi = B.n >= 16 ? (int)((B.n - 16) / 16 + 1 < B.NC ? (B.n - 16) / 16 + 1 : B.NC) : 0;
+  int k = 0;
+  for (; k < B.NC && k < k_lo && ok; ++k) edge_chunk(k);
+  if (k_hi > k_lo && ok) {
+    const __amdgpu_buffer_rsrc_t ry = make_rsrc(g.sy, (uint32_t)(B.n * 4));
+    constexpr int LOAD_DEPTH = 4;
+    u4 buf[LOAD_DEPTH][R][4];
+    auto issue = [&](int kk, u4 (&b)[R][4]) {
+#pragma unroll
+      for (int s = 0; s < R; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int col = 16 * kk + 4 * lq - rho[s][i];
+          b[s][i] = __builtin_amdgcn_raw_buffer_load_b128(ry, kk < k_hi ? (uint32_t)(col * 4) : 0xFFFFFFFFu, 0, 0);
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < LOAD_DEPTH; ++j) issue(k_lo + j, buf[j]);
+    for (int k0 = k_lo; k0 < k_hi && ok; k0 += LOAD_DEPTH) {
+#pragma unroll
+      for (int j = 0; j < LOAD_DEPTH; ++j) {
+        const int kk = k0 + j;
+        if (kk < k_hi && slot_free(kk)) write_slot(kk, buf[j]);
+        issue(kk + LOAD_DEPTH, buf[j]);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): no load still landing in registers
+    k = k_hi;
   }
+  for (; k < B.NC && ok; ++k) edge_chunk(k);
 }
 
 template <int W, int R>
