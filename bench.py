@@ -258,9 +258,9 @@ def dtw_leg(torch, wf, wfgen, step_ns, steps=5):
 
 
 def traceback_leg(torch, wf, cost, steps=3):
-    """The traceback of the 16384 x 16384 benchmark grid: one workgroup walks back from the
-    last cell through 64 x 64 blocks staged in LDS (a sequential path of up to m + n - 1
-    cells; latency-bound)."""
+    """The traceback of the 16384 x 16384 benchmark grid: one wave walks back from the last
+    cell through 64 x 64 blocks held in registers (a sequential path of up to m + n - 1
+    cells, walked on the scalar unit; latency-bound)."""
     H = wf.solve(cost)
     torch.cuda.synchronize()
     ts = []

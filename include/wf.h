@@ -203,7 +203,7 @@ wf_status wf_solve_noalloc(wf_ctx* ctx, const wf_problem* p, void* stream);
  * pairs, (m-1, n-1) first, followed by the outside predecessor the walk ended on
  * ((-1, j), (i, -1) or (-1, -1)); writes the number of visited cells (at most
  * m + n - 1) to `length` (device, one int64).  Asynchronous on `stream` like
- * wf_solve; one workgroup walks the grid in 64 x 64 tiles staged in LDS.
+ * wf_solve; one wave walks the grid in 64 x 64 tiles held in registers.
  * Errors: WF_EINVAL (m or n < 1, NULL out/path/length, ld_out < n). */
 wf_status wf_traceback(wf_ctx* ctx, const wf_problem* p, int32_t* path, int64_t* length, void* stream);
 

@@ -1991,78 +1991,123 @@ void wf_sweep64_kernel(KArgs a) {
 
 // Traceback of a computed grid: from (m-1, n-1), step to the predecessor whose value the
 // rule selects, NW before N before W on equal values, until that predecessor lies
-// outside the grid.  One wave.  It stages in LDS the 64 x 64 block of values whose
-// bottom-right cell is the walk's current cell -- 63 x 63 cells of H and the row above
-// and the column left of them (from H, or the boundary) -- and every lane turns one
-// column of it into predecessor codes; lane 0 then follows the codes until the walk
-// leaves the block, and the wave stages the next one.
+// outside the grid.  One wave.  Lane b holds in registers column j0 - 1 + b of the
+// 64 x 64 block whose bottom-right cell is the walk's current cell: rows i0 - 1 ..
+// i0 + 62, i.e. 63 x 63 cells of H plus the row above and the column left of them (from
+// H, or the boundary).  Each lane turns its column into predecessor codes (0: NW, 1: N,
+// 2: W) with one DPP shift per row for the left neighbour's values, packed two bits per
+// row, 16 rows per register.  The walk runs on the scalar unit: one lane read per step
+// from the register of the current 16 rows, and the step's code shifted into a 64-bit
+// move record; every 32 steps the wave turns the record into (i, j) pairs with a prefix
+// sum over lanes and writes them out.
 constexpr int TB = 64;  // staged block side (63 cells + one boundary row / column)
+
+template <typename T> __device__ __forceinline__ T shr1_any(T x) {
+  if constexpr (sizeof(T) == 8) return dpp_shr1_64(x, x);
+  else return dpp_shr1<T>(x, x);
+}
 
 template <typename T, int RULE>
 __global__ void __launch_bounds__(64) traceback_kernel(const T* H, int64_t ld, int64_t m, int64_t n, const T* top,
                                                        const T* left, int32_t* path, int64_t* length) {
-  __shared__ T blk[TB][TB];            // blk[a][b]: row i0 - 1 + a, column j0 - 1 + b
-  __shared__ uint8_t code[TB][TB];     // 0: NW, 1: N, 2: W
-  __shared__ int64_t s_state[3];
   const int lane = threadIdx.x;
   const T absent = Num<T>::template absent<RULE>();
-  int64_t i = m - 1, j = n - 1, k = 0;
+  int ci = (int)(m - 1), cj = (int)(n - 1);  // the walk's current cell
+  int64_t k = 0;                             // path entries written
+  // Codes of the pending steps, newest in the low bits, above a marker bit: with n steps
+  // pending the marker is bit 2n, so it reaches bit 62 at 31 steps.
+  uint64_t mv = 1;
+  int fi = ci, fj = cj;  // cell of the first pending step
+  // Write the pending steps: step e visited (fi, fj) minus the moves of steps 0 .. e-1.
+  auto flush = [&]() {
+    const int nmv = (63 - __builtin_clzll(mv)) >> 1;
+    const uint32_t c = lane < nmv ? (uint32_t)(mv >> (2 * (nmv - 1 - lane))) & 3u : 3u;
+    const uint32_t d = lane < nmv ? ((1u - (c >> 1)) << 16) | (1u - (c & 1u)) : 0u;  // (rows, cols) moved
+    // Inclusive prefix sum over lanes 0 .. 31 with DPP: within rows of 16, then row 0's
+    // total into row 1.
+    uint32_t inc = d;
+    inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x111, 0xf, 0xf, true);  // row_shr:1
+    inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112, 0xf, 0xf, true);  // row_shr:2
+    inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x114, 0xf, 0xf, true);  // row_shr:4
+    inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x118, 0xf, 0xf, true);  // row_shr:8
+    inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x142, 0xa, 0xf, false); // row_bcast:15
+    const uint32_t ex = inc - d;
+    if (lane < nmv) {
+      path[2 * (k + lane)] = fi - (int)(ex >> 16);
+      path[2 * (k + lane) + 1] = fj - (int)(ex & 0xffffu);
+    }
+    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 31);
+    fi -= (int)(tot >> 16);
+    fj -= (int)(tot & 0xffffu);
+    k += nmv;
+    mv = 1;
+  };
   for (;;) {
-    const int64_t i0 = i - (TB - 2) > 0 ? i - (TB - 2) : 0;
-    const int64_t j0 = j - (TB - 2) > 0 ? j - (TB - 2) : 0;
-    // Lane b stages column j0 - 1 + b of rows i0 - 1 .. i0 + 62 (all loads in flight at once).
+    const int i0 = ci - (TB - 2) > 0 ? ci - (TB - 2) : 0;
+    const int j0 = cj - (TB - 2) > 0 ? cj - (TB - 2) : 0;
+    // Lane b loads column j0 - 1 + b of rows i0 - 1 .. i0 + 62 (all loads in flight at once);
+    // cells below or right of the current cell are never read and stay absent.
     const int64_t col = j0 - 1 + lane;
     T v[TB];
+    if (i0 >= 1 && j0 >= 1) {  // inside the grid and 63 x 63 cells up-left of the current cell
+      const T* p = H + (int64_t)(i0 - 1) * ld + col;
 #pragma unroll
-    for (int a = 0; a < TB; ++a) {
-      const int64_t r = i0 - 1 + a;
-      T x = absent;
-      if (r <= i && col <= j) {
-        if (r < 0) x = top ? top[col + 1] : (col == -1 ? (T)0 : absent);
-        else if (col < 0) x = left ? left[r] : absent;
-        else x = H[r * ld + col];
-      }
-      v[a] = x;
-    }
+      for (int a = 0; a < TB; ++a) v[a] = p[a * ld];
+    } else {
 #pragma unroll
-    for (int a = 0; a < TB; ++a) blk[a][lane] = v[a];
-    __syncthreads();
-    if (lane >= 1) {
-#pragma unroll 4
-      for (int a = 1; a < TB; ++a) {
-        const T nw = blk[a - 1][lane - 1], nn = blk[a - 1][lane], ww = blk[a][lane - 1];
-        T best = nw;
-        uint8_t c = 0;
-        if (RULE == 0 ? nn < best : nn > best) { best = nn; c = 1; }
-        if (RULE == 0 ? ww < best : ww > best) c = 2;
-        code[a][lane] = c;
+      for (int a = 0; a < TB; ++a) {
+        const int64_t r = i0 - 1 + a;
+        T x = absent;
+        if (r <= ci && col <= cj) {
+          if (r < 0) x = top ? top[col + 1] : (col == -1 ? (T)0 : absent);
+          else if (col < 0) x = left ? left[r] : absent;
+          else x = H[r * ld + col];
+        }
+        v[a] = x;
       }
     }
-    __syncthreads();
-    if (lane == 0) {
-      int64_t ci = i, cj = j;
-      while (ci >= i0 && cj >= j0) {
-        path[2 * k] = (int32_t)ci;
-        path[2 * k + 1] = (int32_t)cj;
-        ++k;
-        const uint8_t c = code[ci - i0 + 1][cj - j0 + 1];
-        ci -= c == 2 ? 0 : 1;
-        cj -= c == 1 ? 0 : 1;
-      }
-      s_state[0] = ci;
-      s_state[1] = cj;
-      s_state[2] = k;
+    uint32_t pk[4] = {0u, 0u, 0u, 0u};  // code of row a at bits 2 (a % 16) of pk[a / 16]
+    T wp = shr1_any(v[0]);                // the left neighbour's value in the previous row
+#pragma unroll
+    for (int a = 1; a < TB; ++a) {
+      const T ww = shr1_any(v[a]);
+      const bool n_lt = RULE == 0 ? v[a - 1] < wp : v[a - 1] > wp;
+      const T best = n_lt ? v[a - 1] : wp;
+      const bool w_lt = RULE == 0 ? ww < best : ww > best;
+      pk[a >> 4] |= (w_lt ? 2u : (n_lt ? 1u : 0u)) << (2 * (a & 15));
+      wp = ww;
     }
-    __syncthreads();
-    i = s_state[0];
-    j = s_state[1];
-    k = s_state[2];
-    __syncthreads();
-    if (i < 0 || j < 0) break;
+    // Row r of the block is tracked as the bit-field operand of s_bfe_u32: offset 2 r
+    // (the hardware takes it modulo 32, which is the field of row r in its register),
+    // width 2.
+    constexpr int BFE2 = 2 << 16;
+    int fo = BFE2 + 2 * __builtin_amdgcn_readfirstlane(ci - i0 + 1);
+    int b = __builtin_amdgcn_readfirstlane(cj - j0 + 1);
+#pragma unroll
+    for (int q = 3; q >= 0; --q) {
+      const int lo = BFE2 + 2 * (q == 0 ? 1 : 16 * q);  // stay while row >= 16 q (>= 1)
+      const int cur = (int)pk[q];
+      while (((fo - lo) | (b - 1)) >= 0) {
+        const uint32_t w = (uint32_t)__builtin_amdgcn_readlane(cur, b);
+        uint32_t c;
+        asm("s_bfe_u32 %0, %1, %2" : "=s"(c) : "s"(w), "s"(fo));
+        mv = (mv << 2) | c;
+        uint32_t top = (uint32_t)(mv >> 32);
+        asm("" : "+s"(top));  // a 32-bit scalar compare, not a 64-bit vector one
+        if (__builtin_expect(top >= (1u << 30), 0)) flush();
+        fo -= 2 - (int)(c & 2u);  // NW and N step up a row
+        b -= 1 - (int)(c & 1u);   // NW and W step left a column
+      }
+    }
+    ci = i0 - 1 + ((fo - BFE2) >> 1);
+    cj = j0 - 1 + b;
+    if (ci < 0 || cj < 0) break;
   }
+  flush();
+  // The outside predecessor the walk ended on follows the visited cells.
   if (lane == 0) {
-    path[2 * k] = (int32_t)i;
-    path[2 * k + 1] = (int32_t)j;
+    path[2 * k] = ci;
+    path[2 * k + 1] = cj;
     *length = k;
   }
 }
