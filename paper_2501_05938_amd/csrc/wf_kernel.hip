@@ -1818,6 +1818,35 @@ __device__ __forceinline__ void storer_band64(const GridDesc& g, int band, WaveL
     while (ks < NC && prog >= (16 * (ks + 1) < T_END ? 16 * (ks + 1) : T_END)) {
       const int k = ks;
       const lds_u8* hs = L8(rings->hring) + (k % H64_SLOTS) * (2 * SLAB);
+      // A chunk whose cells all lie inside the grid and left of the last column needs no
+      // bounds checks and touches no edge output but the last row: all eight quads are
+      // read from the ring first, then written with one 16-byte store each (full mode),
+      // and lanes 60..63 (row 63) write theirs to the last-row output when the band ends
+      // the grid.
+      const bool clean = k >= 4 && 16 * k + 15 <= n - 2 && row0 + 63 <= m - 1;
+      const bool to_last_row = row0 + 63 == m - 1 && g.last_row;
+      if (clean) {
+        if (full || to_last_row) {
+          u4 v[2][4];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[h][i] = lds_ld4(hs + SLAB * h + 1024 * i + 16 * lane);
+          if (full) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int r = 16 * i + (lane >> 2);
+              double* op = (double*)g.out + (row0 + r) * g.ld_out + (16 * k + 2 * lq - r);
+#pragma unroll
+              for (int h = 0; h < 2; ++h) *(glb_u4a4*)(op + 8 * h) = v[h][i];
+            }
+          }
+          if (to_last_row && lane >= 60) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) *(glb_u4a4*)((double*)g.last_row + (16 * k + 8 * h + 2 * lq - 63)) = v[h][3];
+          }
+        }
+      } else {
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -1849,6 +1878,7 @@ __device__ __forceinline__ void storer_band64(const GridDesc& g, int band, WaveL
             }
           }
         }
+      }
       if (handoff) {
         // Positions 16k .. 16k + 15 of the bottom row (lane 63's row), the ones in [60, T_END).
         const int p = 16 * k + (lane & 15);
