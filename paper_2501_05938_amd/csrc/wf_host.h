@@ -118,7 +118,7 @@ size_t hand_elems(const wf_problem* p, int bs);
 wfk::KArgs base_args(wf_ctx* ctx, uint32_t* ctl, int64_t nitems);
 // XCD queues for a single-grid launch of nwg workgroups (see KArgs::nx), when the context
 // has them and the launch has a workgroup for every XCD.
-void xcd_queues(const wf_ctx* ctx, wfk::KArgs& a, int nwg, int dtype);
+void xcd_queues(const wf_ctx* ctx, wfk::KArgs& a, int nwg);
 
 }  // namespace wfh
 

@@ -1796,7 +1796,7 @@ __device__ __forceinline__ void loader_band64(const GridDesc& g, int band, WaveL
 // bottom row's positions of the chunk to the handoff row (encoded), then the slot is
 // released; the storer also re-arms the band above's handoff positions behind the feeder.
 __device__ __forceinline__ void storer_band64(const GridDesc& g, int band, WaveLds64* lds, WaveRings64* rings, int lane,
-                                              const KArgs& a) {
+                                              const KArgs& a, bool hand_local) {
   const int64_t m = g.m, n = g.n, row0 = (int64_t)band * 64;
   if (row0 >= m) return;
   WaveLds64& L = lds[0];
@@ -1884,7 +1884,10 @@ __device__ __forceinline__ void storer_band64(const GridDesc& g, int band, WaveL
         const int p = 16 * k + (lane & 15);
         if (lane < 16 && p >= 60 && p < T_END) {
           const uint64_t x = *(const __attribute__((address_space(3))) uint64_t*)(hs + pos_off64(63, lane));
-          __builtin_amdgcn_raw_buffer_store_b128(enc64(__builtin_bit_cast(double, x)), hand_out, p * 16, 0, CPOL_SC1);
+          // Plain stores when the band below runs on this XCD (same L2), system-coherent
+          // ones otherwise.
+          if (hand_local) __builtin_amdgcn_raw_buffer_store_b128(enc64(__builtin_bit_cast(double, x)), hand_out, p * 16, 0, 0);
+          else __builtin_amdgcn_raw_buffer_store_b128(enc64(__builtin_bit_cast(double, x)), hand_out, p * 16, 0, CPOL_SC1);
         }
       }
       ++ks;
@@ -1980,9 +1983,18 @@ void wf_sweep64_kernel(KArgs a) {
   __shared__ uint32_t s_item;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
+  // Per-XCD ticket queues as in the fp32 kernel (single-grid launches only).
+  const uint32_t nx = a.nx > 1 ? (uint32_t)a.nx : 1u, seg = a.seg > 0 ? (uint32_t)a.seg : 1u;
+  const uint32_t xq = nx > 1 ? xcc_id() % nx : 0u;
   for (;;) {
     if (threadIdx.x == 0) {
-      uint32_t t = atomicAdd(&a.ctl[CTL_TICKET], 1u);
+      uint32_t t;
+      if (nx > 1) {
+        const uint32_t q = atomicAdd(&a.ctl[CTL_QUEUE + xq], 1u);
+        t = ((q / seg) * nx + xq) * seg + q % seg;
+      } else {
+        t = atomicAdd(&a.ctl[CTL_TICKET], 1u);
+      }
       if (ld_dev(a.ctl + CTL_ABORT)) t = 0xFFFFFFFFu;
       s_item = t;
     }
@@ -2013,7 +2025,7 @@ void wf_sweep64_kernel(KArgs a) {
     }
     if (wave == 0) compute_band64<RULE>(gd, band, lds, &rings, lane, a);
     else if (wave == 1) loader_band64(gd, band, lds, &rings, lane, a);
-    else if (wave == 2) storer_band64(gd, band, lds, &rings, lane, a);
+    else if (wave == 2) storer_band64(gd, band, lds, &rings, lane, a, nx > 1 && ((t + 1u) / seg) % nx == xq);
     else feeder_band64<RULE>(gd, band, lds, lane, a);
     __syncthreads();
   }

@@ -294,9 +294,9 @@ size_t wfh::hand_elems(const wf_problem* p, int bs) {
   return nb > 1 ? (size_t)(nb - 1) * (size_t)hand_ld_for(p->n, shape_rows_per_lane(bs)) * words : 0;
 }
 
-void wfh::xcd_queues(const wf_ctx* ctx, KArgs& a, int nwg, int dtype) {
+void wfh::xcd_queues(const wf_ctx* ctx, KArgs& a, int nwg) {
   const int nx = ctx->nx;
-  if (nx < 2 || nwg < nx || dtype == WF_F64 || a.grids || xcd_off.load()) return;
+  if (nx < 2 || nwg < nx || a.grids || xcd_off.load()) return;
   // Runs of seg bands per XCD: at most one band per workgroup of the XCD's queue at a
   // time, and the grid's bands spread over all XCDs.
   const int64_t per_xcd = (a.nitems + nx - 1) / nx;
@@ -559,7 +559,7 @@ static wf_status solve_one(wf_ctx* ctx, const wf_problem* p, int bs, int max_wgs
   const int resident = ctx->num_cus * wgs_per_cu(bs, p->dtype);
   int nwg = (int)std::min<int64_t>(a.nitems, resident);
   if (max_wgs > 0) nwg = std::min(nwg, max_wgs);
-  xcd_queues(ctx, a, nwg, p->dtype);
+  xcd_queues(ctx, a, nwg);
   // Optional trace (profiling hook): WF_TRACE_FILE=<path> makes wf_solve synchronous
   // and writes TRACE_WORDS uint64 per (band, compute wave) to <path>.
   const char* trace_file = std::getenv("WF_TRACE_FILE");
@@ -659,7 +659,7 @@ extern "C" wf_status wf_solve_noalloc(wf_ctx* ctx, const wf_problem* p, void* st
   a.g0 = make_desc(p, bs, s.hand);
   a.nitems = a.g0.nbands;
   const int nwg = (int)std::min<int64_t>(a.nitems, (int64_t)ctx->num_cus * wgs_per_cu(bs, p->dtype));
-  xcd_queues(ctx, a, nwg, p->dtype);
+  xcd_queues(ctx, a, nwg);
   WF_HIP(launch_noalloc_prep(s.ctl, s.needs_rearm, s.hand, sentinel_of(p->dtype), (int64_t)need, stream));
   s.needs_rearm = false;
   WF_HIP(launch_shape(p->dtype, p->rule, bs, nwg, a, stream));
