@@ -2129,7 +2129,7 @@ __global__ void __launch_bounds__(64) traceback_kernel(const T* H, int64_t ld, i
     for (int q = 3; q >= 0; --q) {
       const int lo = BFE2 + 2 * (q == 0 ? 1 : 16 * q);  // stay while row >= 16 q (>= 1)
       const int cur = (int)pk[q];
-      while (((fo - lo) | (b - 1)) >= 0) {
+      auto step = [&]() {
         const uint32_t w = (uint32_t)__builtin_amdgcn_readlane(cur, b);
         uint32_t c;
         asm("s_bfe_u32 %0, %1, %2" : "=s"(c) : "s"(w), "s"(fo));
@@ -2139,6 +2139,12 @@ __global__ void __launch_bounds__(64) traceback_kernel(const T* H, int64_t ld, i
         if (__builtin_expect(top >= (1u << 30), 0)) flush();
         fo -= 2 - (int)(c & 2u);  // NW and N step up a row
         b -= 1 - (int)(c & 1u);   // NW and W step left a column
+      };
+      // Two steps per pass: one taken branch per two steps (four measure the same).
+      while (((fo - lo) | (b - 1)) >= 0) {
+        step();
+        if (((fo - lo) | (b - 1)) < 0) break;
+        step();
       }
     }
     ci = i0 - 1 + ((fo - BFE2) >> 1);
