@@ -553,8 +553,31 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
     WF_CHUNK(0, k, cA, tA, cB, tB);
     WF_CHUNK(0, k + 1, cB, tB, cA, tA);
   }
-  // Every later chunk, two per pass so the register sets alternate without copies (k is
-  // even here, so a last odd chunk uses set A).
+  // Every later chunk, an even number per pass so the register sets alternate without
+  // copies (k stays even, so a last odd chunk uses set A): two per pass until k is a
+  // multiple of 8, then eight per pass with k written as 8 j, so that each chunk's c and
+  // H ring slots ((k + i) mod 8) are compile-time constants and their LDS addresses
+  // become instruction offsets; two per pass for the rest.
+  static_assert(C_SLOTS == 8 && H_SLOTS == 8, "eight chunks per pass cover each ring once");
+  for (; (k & 7) != 0 && k + 1 < NCc; k += 2) {
+    WF_CHUNK(1, k, cA, tA, cB, tB);
+    WF_CHUNK(1, k + 1, cB, tB, cA, tA);
+  }
+  if ((k & 7) == 0) {
+    int j = k >> 3;
+    for (; 8 * j + 7 < NCc; ++j) {
+      const int kb = 8 * j;
+      WF_CHUNK(1, kb, cA, tA, cB, tB);
+      WF_CHUNK(1, kb + 1, cB, tB, cA, tA);
+      WF_CHUNK(1, kb + 2, cA, tA, cB, tB);
+      WF_CHUNK(1, kb + 3, cB, tB, cA, tA);
+      WF_CHUNK(1, kb + 4, cA, tA, cB, tB);
+      WF_CHUNK(1, kb + 5, cB, tB, cA, tA);
+      WF_CHUNK(1, kb + 6, cA, tA, cB, tB);
+      WF_CHUNK(1, kb + 7, cB, tB, cA, tA);
+    }
+    k = 8 * j;
+  }
   for (; k + 1 < NCc; k += 2) {
     WF_CHUNK(1, k, cA, tA, cB, tB);
     WF_CHUNK(1, k + 1, cB, tB, cA, tA);
