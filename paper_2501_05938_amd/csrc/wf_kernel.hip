@@ -94,6 +94,7 @@ struct alignas(16) WaveLds {
   uint64_t tr_t_wait;       // compute cycles waiting for T quads
   uint64_t tr_load_wait;    // loader cycles waiting for a free c slot
   uint64_t tr_pad;
+  uint64_t sink[64];        // lanes 1..63's half of the per-chunk progress store (never read)
 };
 
 template <int R>
@@ -410,8 +411,8 @@ template <typename T, int RULE, int R, int KIND, int CONS, bool MASK, bool LOCAL
 __device__ __forceinline__ void compute_chunk(
     int k, int G, int gT, int NCc, WaveLds* lds, WaveLds& L, WaveLds* C,
     __amdgpu_buffer_rsrc_t hand_out, const lds_u8* const (&cq)[4], lds_u8* const (&hq)[4], lds_u8* ct_base,
-    const lds_u8* hrd, bool lane63, int lane, const u4 (&cc)[R][4], u4 (&tc)[4], u4 (&cn)[R][4], u4 (&tn)[4],
-    uint32_t& tprev_w,
+    const lds_u8* hrd, lds_u8* prog_at, bool lane63, int lane, const u4 (&cc)[R][4], u4 (&tc)[4], u4 (&cn)[R][4],
+    u4 (&tn)[4], uint32_t& tprev_w,
     T (&H)[R], T (&Hp)[R], T& Np, CtlSnap& snap, const KArgs& a, uint64_t* crec) {
   const int pos = CHUNK * k;
   // Keep the chunk-start check (and the scalar copies of the control snapshot it takes)
@@ -427,10 +428,10 @@ __device__ __forceinline__ void compute_chunk(
   // this chunk's T quads are in registers, so the feeder (or the compute wave above) may
   // reuse their slots (t_reset); as the compute wave above the consumer, also how far
   // the consumer's T ring is written: every position of the earlier chunks.
-  if (lane == 0) {
-    *(volatile lds_u2*)L8(&L.progress) = u2{(uint32_t)pos, (uint32_t)(pos + 64 * R + CHUNK)};
-    if (CONS == 1) st_ctl(&C->t_fed, (uint32_t)pos);
-  }
+  // Every lane stores, so the store needs no exec change: lane 0 to the control words
+  // (prog_at), the others to the wave's sink.
+  *(volatile lds_u2*)prog_at = u2{(uint32_t)pos, (uint32_t)(pos + 64 * R + CHUNK)};
+  if (CONS == 1 && lane == 0) st_ctl(&C->t_fed, (uint32_t)pos);
   if (rec && lane == 0) rec[9] = wall_clock64();
   read_c<R>(k + 1, cq, cn);
   const int hb = (k % H_SLOTS) * (R * SLAB);
@@ -516,6 +517,7 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   const int NCc = (4 * G + CHUNK - 1) / CHUNK;
   lds_u8* ct_base = CONS == 1 ? L8(C->tring) : nullptr;
   const bool lane63 = lane == 63;
+  lds_u8* const prog_at = lane == 0 ? L8(&L.progress) : L8(&L.sink[lane]);
   constexpr int TF = t_first(R);
   // First T quad: columns -3..0 of the row above (.z is the corner, .w column 0), read
   // once the ring holds it.
@@ -544,8 +546,8 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   chunk_gate<R, CONS>(0, NCc, lds, L, C, snap, tA, a, lane, chunk_trace(crec, 0));
 #define WF_CHUNK(KIND, KK, CUR_C, CUR_T, NXT_C, NXT_T)                                                         \
   compute_chunk<T, RULE, R, KIND, CONS, MASK, LOCAL>(KK, G, gT, NCc, lds, L, C, hand_out, cq, hq, ct_base, hrd,      \
-                                                    lane63, lane, CUR_C, CUR_T, NXT_C, NXT_T, tprev_w, H, Hp, Np, snap, \
-                                                    a, crec)
+                                                    prog_at, lane63, lane, CUR_C, CUR_T, NXT_C, NXT_T, tprev_w, H, Hp, \
+                                                    Np, snap, a, crec)
   int k = 0;
   // The first 4 R chunks (groups 0 .. 16 R - 1, where rows left of column 0 are masked;
   // a walk always has at least that many).
