@@ -2065,7 +2065,7 @@ void wf_sweep64_kernel(KArgs a) {
 // 2: W) with one DPP shift per row for the left neighbour's values, packed two bits per
 // row, 16 rows per register.  The walk runs on the scalar unit: one lane read per step
 // from the register of the current 16 rows, and the step's code shifted into a 64-bit
-// move record; every 32 steps the wave turns the record into (i, j) pairs with a prefix
+// move record; every 31 steps the wave turns the record into (i, j) pairs with a prefix
 // sum over lanes and writes them out.
 constexpr int TB = 64;  // staged block side (63 cells + one boundary row / column)
 
