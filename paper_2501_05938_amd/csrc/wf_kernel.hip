@@ -413,7 +413,7 @@ __device__ __forceinline__ void compute_chunk(
     __amdgpu_buffer_rsrc_t hand_out, const lds_u8* const (&cq)[4], lds_u8* const (&hq)[4], lds_u8* ct_base,
     const lds_u8* hrd, lds_u8* prog_at, bool lane63, int lane, const u4 (&cc)[R][4], u4 (&tc)[4], u4 (&cn)[R][4],
     u4 (&tn)[4], uint32_t& tprev_w,
-    T (&H)[R], T (&Hp)[R], T& Np, CtlSnap& snap, const KArgs& a, uint64_t* crec) {
+    T (&H)[R], T (&Hp)[R], T& Np, CtlSnap& snap, const KArgs& a, uint64_t* crec, bool more) {
   const int pos = CHUNK * k;
   // Keep the chunk-start check (and the scalar copies of the control snapshot it takes)
   // from being scheduled into the previous chunk's walk.
@@ -506,7 +506,8 @@ __device__ __forceinline__ void compute_chunk(
           wall_clock64();
   }
   // The next chunk's start conditions, on the snapshot read during the last group.
-  if (k + 1 < NCc) chunk_gate<R, CONS>(k + 1, NCc, lds, L, C, snap, tn, a, lane, chunk_trace(crec, k + 1));
+  // (more: chunk k + 1 exists; a constant where the caller's loop bound says so)
+  if (more) chunk_gate<R, CONS>(k + 1, NCc, lds, L, C, snap, tn, a, lane, chunk_trace(crec, k + 1));
 }
 
 template <typename T, int RULE, int R, int CONS, bool MASK, bool LOCAL>
@@ -544,10 +545,12 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   snap_ctl<CONS>(L, C, snap);
   read_t<R>(0, L8(L.tring), tA);  // after the snapshot, as in every chunk
   chunk_gate<R, CONS>(0, NCc, lds, L, C, snap, tA, a, lane, chunk_trace(crec, 0));
-#define WF_CHUNK(KIND, KK, CUR_C, CUR_T, NXT_C, NXT_T)                                                         \
+#define WF_CHUNK_M(KIND, KK, CUR_C, CUR_T, NXT_C, NXT_T, MORE)                                                 \
   compute_chunk<T, RULE, R, KIND, CONS, MASK, LOCAL>(KK, G, gT, NCc, lds, L, C, hand_out, cq, hq, ct_base, hrd,      \
                                                     prog_at, lane63, lane, CUR_C, CUR_T, NXT_C, NXT_T, tprev_w, H, Hp, \
-                                                    Np, snap, a, crec)
+                                                    Np, snap, a, crec, MORE)
+#define WF_CHUNK(KIND, KK, CUR_C, CUR_T, NXT_C, NXT_T) \
+  WF_CHUNK_M(KIND, KK, CUR_C, CUR_T, NXT_C, NXT_T, (KK) + 1 < NCc)
   int k = 0;
   // The first 4 R chunks (groups 0 .. 16 R - 1, where rows left of column 0 are masked;
   // a walk always has at least that many).
@@ -569,13 +572,14 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
     int j = k >> 3;
     for (; 8 * j + 7 < NCc; ++j) {
       const int kb = 8 * j;
-      WF_CHUNK(1, kb, cA, tA, cB, tB);
-      WF_CHUNK(1, kb + 1, cB, tB, cA, tA);
-      WF_CHUNK(1, kb + 2, cA, tA, cB, tB);
-      WF_CHUNK(1, kb + 3, cB, tB, cA, tA);
-      WF_CHUNK(1, kb + 4, cA, tA, cB, tB);
-      WF_CHUNK(1, kb + 5, cB, tB, cA, tA);
-      WF_CHUNK(1, kb + 6, cA, tA, cB, tB);
+      // Chunks kb .. kb + 6 always have a successor (kb + 7 < NCc).
+      WF_CHUNK_M(1, kb, cA, tA, cB, tB, true);
+      WF_CHUNK_M(1, kb + 1, cB, tB, cA, tA, true);
+      WF_CHUNK_M(1, kb + 2, cA, tA, cB, tB, true);
+      WF_CHUNK_M(1, kb + 3, cB, tB, cA, tA, true);
+      WF_CHUNK_M(1, kb + 4, cA, tA, cB, tB, true);
+      WF_CHUNK_M(1, kb + 5, cB, tB, cA, tA, true);
+      WF_CHUNK_M(1, kb + 6, cA, tA, cB, tB, true);
       WF_CHUNK(1, kb + 7, cB, tB, cA, tA);
     }
     k = 8 * j;
@@ -586,6 +590,7 @@ __device__ __forceinline__ void compute_walk(int G, int gT, WaveLds* lds, WaveLd
   }
   if (k < NCc) WF_CHUNK(1, k, cA, tA, cB, tB);
 #undef WF_CHUNK
+#undef WF_CHUNK_M
   const int t_pad = t_pad_end(G, R);
   if (CONS == 1) {
     // The consumer's last chunks read T positions [16 NCc, t_pad), past every group of
